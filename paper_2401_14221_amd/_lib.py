@@ -1,0 +1,176 @@
+"""ctypes binding of libp2r.so; same names and arguments as include/p2r.h."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libp2r.so")
+_HEADER = os.path.join(os.path.dirname(_HERE), "include", "p2r.h")
+
+P2R_OK, P2R_EINVAL, P2R_ELAYOUT, P2R_EHIP, P2R_ENOTUNED = 0, -1, -2, -3, -4
+ST_NO_CROSSING = 1 << 0
+ST_NEWTON_FAIL = 1 << 1
+ST_FP64_FALLBACK = 1 << 2
+ST_S_NOT_PD = 1 << 3
+ST_BAD_INPUT = 1 << 4
+ST_ML_REJECTED = 1 << 5
+ST_HIT_MISSING = 1 << 6
+ST_CHI2_CUT = 1 << 7
+ST_DONE = 1 << 31
+
+
+class P2RError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libp2r error {code}: {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("bz_tesla", C.c_float), ("newton_tol_cm", C.c_float), ("newton_max_iter", C.c_int32),
+                ("chi2_cut", C.c_float), ("fp64_fallback", C.c_int32), ("width", C.c_int32),
+                ("mlp", C.c_void_p)]
+
+
+_lib = None
+vp = C.c_void_p
+
+
+def library_path() -> str:
+    return _SO
+
+
+def library():
+    """Load libp2r.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError(f"{_SO} is missing: build it with python paper_2401_14221_amd/build.py")
+        L = C.CDLL(_SO)
+        i32, i64 = C.c_int32, C.c_int64
+        L.p2r_opts_default.argtypes = [C.POINTER(Opts)]
+        L.p2r_opts_default.restype = None
+        L.p2r_last_error.restype = C.c_char_p
+        L.p2r_version.restype = C.c_char_p
+        L.p2r_ctx_create.argtypes = [C.POINTER(vp), C.c_int, C.c_char_p]
+        L.p2r_ctx_destroy.argtypes = [vp]
+        L.p2r_ctx_destroy.restype = None
+        L.p2r_layout_width.argtypes = [vp, C.c_int, C.POINTER(i32)]
+        L.p2r_variant_name.argtypes = [vp, C.c_int]
+        L.p2r_variant_name.restype = C.c_char_p
+        for f in (L.p2r_propagate_update, L.p2z_propagate_update):
+            f.argtypes = [vp, C.POINTER(Opts), i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.p2r_autotune.argtypes = [vp, C.c_int, i32, i32, vp]
+        if hasattr(L, "fit_tracks_batched"):
+            L.fit_tracks_batched.argtypes = [vp, C.POINTER(Opts), i32] + [vp] * 13
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names of the functions include/p2r.h declares."""
+    txt = open(_HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\(", txt, flags=re.M)) - {"defined"})
+
+
+def _check(rc):
+    if rc != 0:
+        raise P2RError(rc, library().p2r_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    library().p2r_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """A libp2r context on one device (tuned variants, workspace, graphs)."""
+
+    def __init__(self, device: int = 0, tune_cache: str | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libp2r needs a HIP GPU; none is visible")
+        self.device = device
+        self._h = vp()
+        _check(library().p2r_ctx_create(C.byref(self._h), device,
+                                        tune_cache.encode() if tune_cache else None))
+
+    def close(self):
+        if self._h:
+            library().p2r_ctx_destroy(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- info
+    def layout_width(self, which: int = 0) -> int:
+        w = C.c_int32()
+        _check(library().p2r_layout_width(self._h, which, C.byref(w)))
+        return w.value
+
+    def variant_name(self, which: int = 0) -> str:
+        return library().p2r_variant_name(self._h, which).decode()
+
+    def autotune(self, which: int, n_tracks: int, n_layers: int, stream=None):
+        _check(library().p2r_autotune(self._h, which, n_tracks, n_layers, _stream(stream)))
+
+    # --------------------------------------------------------------- fits
+    def _outputs(self, trk_in, n):
+        dev = trk_in.device
+        return (torch.empty_like(trk_in), torch.empty(n, dtype=torch.float32, device=dev),
+                torch.empty(n, dtype=torch.int32, device=dev))
+
+    def p2r_propagate_update(self, n_tracks, layer_r, trk_in, hits, out=None, opts=None, stream=None, **kw):
+        """p2r fit of AoSoA tracks; returns (trk_out, chi2, status) device tensors."""
+        opts = opts or default_opts(**kw)
+        trk_out, chi2, status = out if out is not None else self._outputs(trk_in, n_tracks)
+        _check(library().p2r_propagate_update(self._h, C.byref(opts), n_tracks, layer_r.numel(), _ptr(layer_r),
+                                              _ptr(trk_in), _ptr(hits), _ptr(trk_out), _ptr(chi2),
+                                              _ptr(status), _stream(stream)))
+        return trk_out, chi2, status
+
+    def p2z_propagate_update(self, n_tracks, layer_z, trk_in, hits, out=None, opts=None, stream=None, **kw):
+        opts = opts or default_opts(**kw)
+        trk_out, chi2, status = out if out is not None else self._outputs(trk_in, n_tracks)
+        _check(library().p2z_propagate_update(self._h, C.byref(opts), n_tracks, layer_z.numel(), _ptr(layer_z),
+                                              _ptr(trk_in), _ptr(hits), _ptr(trk_out), _ptr(chi2),
+                                              _ptr(status), _stream(stream)))
+        return trk_out, chi2, status
+
+    def fit_tracks_batched(self, offsets, surf_type, surf_val, hit_pos, hit_cov, par_in, cov_in, q,
+                           out=None, opts=None, stream=None, **kw):
+        """Ragged CSR fit; returns (par_out, cov_out, chi2, status)."""
+        opts = opts or default_opts(**kw)
+        n = par_in.shape[0]
+        dev = par_in.device
+        if out is None:
+            out = (torch.empty((n, 6), dtype=torch.float32, device=dev),
+                   torch.empty((n, 21), dtype=torch.float32, device=dev),
+                   torch.empty(n, dtype=torch.float32, device=dev),
+                   torch.empty(n, dtype=torch.int32, device=dev))
+        par_out, cov_out, chi2, status = out
+        _check(library().fit_tracks_batched(self._h, C.byref(opts), n, _ptr(offsets), _ptr(surf_type),
+                                            _ptr(surf_val), _ptr(hit_pos), _ptr(hit_cov), _ptr(par_in),
+                                            _ptr(cov_in), _ptr(q), _ptr(par_out), _ptr(cov_out), _ptr(chi2),
+                                            _ptr(status), _stream(stream)))
+        return par_out, cov_out, chi2, status

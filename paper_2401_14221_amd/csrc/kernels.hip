@@ -1,0 +1,251 @@
+// Fit kernels for gfx950: one lane per track, the whole layer loop in one
+// launch (the paper's single fused kernel, Section 2).  Track records are
+// read once, coalesced, into registers; hits stream in per layer, the next
+// layer's hit prefetched while the current layer is computed; results are
+// written once at the end.
+#include "launch.h"
+#include "track_math.h"
+
+namespace p2r {
+
+__device__ __forceinline__ void load_track(const float* __restrict__ t, int W, State& st) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f) st.p[f] = t[f * W];
+#pragma unroll
+    for (int f = 0; f < 21; ++f) st.c[f] = t[(6 + f) * W];
+    st.q = t[27 * W];
+}
+
+__device__ __forceinline__ void store_track(float* __restrict__ t, int W, const State& st) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f) t[f * W] = st.p[f];
+#pragma unroll
+    for (int f = 0; f < 21; ++f) t[(6 + f) * W] = st.c[f];
+    t[27 * W] = st.q;
+}
+
+// p2r: hits [block][layer][9][W]
+template <int W, int UNROLL>
+__device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.n) return;
+    const int b = gid / W, l = gid % W;
+    const float* tin = a.trk_in + (size_t)b * (28 * W) + l;
+    State st;
+    load_track(tin, W, st);
+    uint32_t flags = 0;
+    int nused = 0;
+    float chi2 = 0.0f;
+    if (bad_input(st)) {
+        flags = ST_BAD_INPUT;
+    } else {
+        const float* hb = a.hits + (size_t)b * ((size_t)a.L * 9 * W) + l;
+        float hm[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
+#pragma unroll UNROLL
+        for (int ly = 0; ly < a.L; ++ly) {
+            const float m[3] = {hm[0], hm[1], hm[2]};
+            const float V[6] = {hm[3], hm[4], hm[5], hm[6], hm[7], hm[8]};
+            if (ly + 1 < a.L) {
+                const float* hn = hb + (size_t)(ly + 1) * (9 * W);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) hm[k] = hn[k * W];
+            }
+            const float R = a.surf[ly];
+            float c2 = 0.0f;
+            StepOut o = step_cylinder(st, R, m, V, P, c2, newton_tol(P.tol, R), -1.0f);
+            flags |= o.flags;
+            if (o.updated) { ++nused; chi2 += c2; }
+        }
+    }
+    store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
+    a.chi2[gid] = chi2;
+    a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
+}
+
+// p2z: W = 64, hits [layer][block][9][64]; disk sign from the input theta
+template <int UNROLL>
+__device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
+    constexpr int W = 64;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.n) return;
+    const int b = gid / W, l = gid % W;
+    const int nb = (a.n + W - 1) / W;
+    const float* tin = a.trk_in + (size_t)b * (28 * W) + l;
+    State st;
+    load_track(tin, W, st);
+    uint32_t flags = 0;
+    int nused = 0;
+    float chi2 = 0.0f;
+    if (bad_input(st)) {
+        flags = ST_BAD_INPUT;
+    } else {
+        const float zsign = st.p[5] < HALF_PI_F ? 1.0f : -1.0f;
+        const size_t lstride = (size_t)nb * (9 * W);
+        const float* hb = a.hits + (size_t)b * (9 * W) + l;
+        float hm[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
+#pragma unroll UNROLL
+        for (int ly = 0; ly < a.L; ++ly) {
+            const float m[3] = {hm[0], hm[1], hm[2]};
+            const float V[6] = {hm[3], hm[4], hm[5], hm[6], hm[7], hm[8]};
+            if (ly + 1 < a.L) {
+                const float* hn = hb + (size_t)(ly + 1) * lstride;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) hm[k] = hn[k * W];
+            }
+            float c2 = 0.0f;
+            StepOut o = step_plane(st, zsign * a.surf[ly], m, V, P, c2);
+            flags |= o.flags;
+            if (o.updated) { ++nused; chi2 += c2; }
+        }
+    }
+    store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
+    a.chi2[gid] = chi2;
+    a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
+}
+
+#define P2R_KERNEL(W, WPE, U)                                                              \
+    __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256),                \
+                                   amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))               \
+    p2r_w##W##_e##WPE##_u##U(FitLaunch a, Params P) { p2r_body<W, U>(a, P); }
+
+#define P2Z_KERNEL(WPE, U)                                                                 \
+    __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256),                \
+                                   amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))               \
+    p2z_w64_e##WPE##_u##U(FitLaunch a, Params P) { p2z_body<U>(a, P); }
+
+P2R_KERNEL(32, 0, 1)
+P2R_KERNEL(64, 0, 1)
+P2R_KERNEL(128, 0, 1)
+P2R_KERNEL(256, 0, 1)
+P2R_KERNEL(64, 4, 1)
+P2R_KERNEL(64, 5, 1)
+P2R_KERNEL(64, 0, 2)
+P2R_KERNEL(128, 4, 1)
+P2R_KERNEL(256, 4, 1)
+P2Z_KERNEL(0, 1)
+P2Z_KERNEL(4, 1)
+P2Z_KERNEL(5, 1)
+P2Z_KERNEL(0, 2)
+
+#define VAR(WH, W, E, U, K) Variant{WH, W, E, U, #K, (const void*)&K}
+
+const std::vector<Variant>& variants() {
+    static const std::vector<Variant> v = {
+        VAR(0, 64, 0, 1, p2r_w64_e0_u1),   // default p2r
+        VAR(0, 32, 0, 1, p2r_w32_e0_u1),
+        VAR(0, 128, 0, 1, p2r_w128_e0_u1),
+        VAR(0, 256, 0, 1, p2r_w256_e0_u1),
+        VAR(0, 64, 4, 1, p2r_w64_e4_u1),
+        VAR(0, 64, 5, 1, p2r_w64_e5_u1),
+        VAR(0, 64, 0, 2, p2r_w64_e0_u2),
+        VAR(0, 128, 4, 1, p2r_w128_e4_u1),
+        VAR(0, 256, 4, 1, p2r_w256_e4_u1),
+        VAR(1, 64, 0, 1, p2z_w64_e0_u1),   // default p2z
+        VAR(1, 64, 4, 1, p2z_w64_e4_u1),
+        VAR(1, 64, 5, 1, p2z_w64_e5_u1),
+        VAR(1, 64, 0, 2, p2z_w64_e0_u2),
+    };
+    return v;
+}
+
+hipError_t launch_fit(const Variant& v, const FitLaunch& a, const Params& P, hipStream_t s) {
+    const int threads = 256;
+    const int blocks = (a.n + threads - 1) / threads;
+    if (blocks == 0) return hipSuccess;
+    FitLaunch aa = a;
+    Params pp = P;
+    void* args[] = {&aa, &pp};
+    return hipLaunchKernel(v.fn, dim3(blocks), dim3(threads), args, 0, s);
+}
+
+
+// ----------------------------------------------------------- autotune data
+// Plausible tracks for timing the variants: counter-hashed uniforms give
+// pT in [0.5, 10] GeV, phi in (-pi, pi], eta in [-1.5, 1.5] (p2r) or
+// |eta| in [1.7, 2.5] (p2z); the hits are the exact crossings of the
+// unsmeared track (surfaces evenly spaced in r = 2.5..110 cm or
+// |z| = 30..270 cm).
+__device__ __forceinline__ float hash_u01(uint32_t a, uint32_t b) {
+    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
+    return (h >> 8) * (1.0f / 16777216.0f);
+}
+
+__global__ void synth_kernel(int which, int W, int32_t n, int32_t L, float* surf, float* trk, float* hits) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < L) {
+        float t = L > 1 ? (float)gid / (float)(L - 1) : 0.0f;
+        surf[gid] = which == 0 ? 2.5f + t * 107.5f : 30.0f + t * 240.0f;
+    }
+    if (gid >= n) return;
+    const int b = gid / W, l = gid % W;
+    const int nb = (n + W - 1) / W;
+    float pt = 0.5f + 9.5f * hash_u01(gid, 1);
+    float eta = which == 0 ? -1.5f + 3.0f * hash_u01(gid, 2)
+                           : (1.7f + 0.8f * hash_u01(gid, 2)) * (hash_u01(gid, 5) < 0.5f ? -1.0f : 1.0f);
+    float phi = -PI_F + TWO_PI_F * hash_u01(gid, 3);
+    float q = hash_u01(gid, 4) < 0.5f ? -1.0f : 1.0f;
+    State st;
+    st.p[0] = 0.0f; st.p[1] = 0.0f; st.p[2] = 0.0f;
+    st.p[3] = 1.0f / pt; st.p[4] = phi; st.p[5] = 2.0f * atanf(expf(-eta));
+    for (int k = 0; k < 21; ++k) st.c[k] = 0.0f;
+    st.c[I21(0, 0)] = 0.01f; st.c[I21(1, 1)] = 0.01f; st.c[I21(2, 2)] = 1.0f;
+    st.c[I21(3, 3)] = 1e-4f; st.c[I21(4, 4)] = 1e-4f; st.c[I21(5, 5)] = 1e-4f;
+    st.q = q;
+    float* t = trk + (size_t)b * 28 * W + l;
+    store_track(t, W, st);
+    float x = 0.f, y = 0.f, z = 0.f, ph = phi;
+    const float kq = -q * KAPPA * 3.8f;
+    const float w = kq / pt;
+    const float cot = 1.0f / tanf(st.p[5]);
+    bool alive = true;
+    for (int ly = 0; ly < L; ++ly) {
+        float S = which == 0 ? 2.5f + (L > 1 ? (float)ly / (float)(L - 1) : 0.0f) * 107.5f
+                             : 30.0f + (L > 1 ? (float)ly / (float)(L - 1) : 0.0f) * 240.0f;
+        float m[3] = {NAN, NAN, NAN};
+        float sphi, cphi;
+        sincosf(ph, &sphi, &cphi);
+        if (alive) {
+            HelixPt h;
+            float s = 0.0f;
+            int it = 0;
+            bool ok;
+            if (which == 0) {
+                ok = cylinder_reachable(x, y, cphi, sphi, w, S) &&
+                     newton_cylinder(x, y, cphi, sphi, w, S, newton_tol(1e-6f, S), 16,
+                                     line_path(x, y, cphi, sphi, S), s, h, it);
+            } else {
+                float Z = eta > 0 ? S : -S;
+                s = (Z - z) / cot;
+                ok = s > 0.0f;
+                if (ok) helix_at(x, y, cphi, sphi, w, s, h);
+            }
+            if (ok) {
+                x = h.x; y = h.y; z = which == 0 ? z + s * cot : (eta > 0 ? S : -S);
+                ph = ph + 2.0f * h.u;
+                m[0] = x; m[1] = y; m[2] = z;
+            } else {
+                alive = false;
+            }
+        }
+        float* hp = which == 0 ? hits + ((size_t)b * L + ly) * 9 * W + l
+                               : hits + ((size_t)ly * nb + b) * 9 * W + l;
+        const float V[6] = {1e-4f, 0.0f, 1e-4f, 0.0f, 0.0f, which == 0 ? 1e-2f : 1e-4f};
+        for (int k = 0; k < 3; ++k) hp[k * W] = m[k];
+        for (int k = 0; k < 6; ++k) hp[(3 + k) * W] = V[k];
+    }
+}
+
+hipError_t launch_synth(int which, int W, int32_t n, int32_t L, float* surf, float* trk, float* hits,
+                        hipStream_t s) {
+    int m = n > L ? n : L;
+    int blocks = (m + 255) / 256;
+    hipLaunchKernelGGL(synth_kernel, dim3(blocks), dim3(256), 0, s, which, W, n, L, surf, trk, hits);
+    return hipGetLastError();
+}
+
+}  // namespace p2r

@@ -1,0 +1,504 @@
+// Device arithmetic of one track-layer step in FP32, one lane per track.
+//
+// State p = (x, y, z, ipt = 1/pT, phi, theta), charge q; covariance kept
+// packed as 21 registers (lower triangle, row-major).  The step follows the
+// method's order (paper, Section 2): propagate the state to the surface,
+// transport the covariance with the Jacobian, then Kalman-update with the
+// surface's 3D hit.  Formulas are the textbook helix in a uniform field and
+// the linear Kalman filter; see the function comments for each form used.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace p2r {
+
+constexpr float KAPPA = 2.99792458e-3f;   // GeV / (T cm)
+constexpr float PI_F = 3.14159265358979f;
+constexpr float TWO_PI_F = 6.28318530717959f;
+constexpr float INV_TWO_PI_F = 0.159154943091895f;
+constexpr float HALF_PI_F = 1.57079632679490f;
+
+enum : uint32_t {
+    ST_NO_CROSSING = 1u << 0,
+    ST_NEWTON_FAIL = 1u << 1,
+    ST_FP64_FALLBACK = 1u << 2,
+    ST_S_NOT_PD = 1u << 3,
+    ST_BAD_INPUT = 1u << 4,
+    ST_ML_REJECTED = 1u << 5,
+    ST_HIT_MISSING = 1u << 6,
+    ST_CHI2_CUT = 1u << 7,
+    ST_DONE = 1u << 31,
+};
+constexpr int NUSED_SHIFT = 8;
+
+// Relative pivot thresholds of the positive-definiteness test of S (a
+// pivot d_k must exceed tau * S_kk).  FP32: below 1e-3 the FP32 inverse
+// would carry more than ~1e-4 relative error, so the FP64 inversion takes
+// over.  FP64: S is formed from FP32 covariance values (relative error
+// >= 6e-8), so pivots below 1e-6 of the diagonal carry no information and S
+// is treated as singular.
+constexpr float PD_TAU32 = 1e-3f;
+constexpr double PD_TAU64 = 1e-6;
+
+// packed index of (i, j), j <= i
+constexpr int I21(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+struct Params {
+    float bz;
+    float tol;
+    int32_t max_iter;
+    float chi2_cut;
+    int32_t fp64_fallback;
+};
+
+struct State {
+    float p[6];
+    float c[21];
+    float q;
+};
+
+// ---------------------------------------------------------------- helix
+// Point of the helix at transverse path s, in the half-angle form
+//   u = omega s / 2,  chord = s sin(u)/u,  phi_m = phi + u,
+//   x' = x + chord cos(phi_m),  y' = y + chord sin(phi_m),  phi' = phi + 2u,
+// which is exact and free of cancellation as omega -> 0.  For |u| < 0.5 the
+// sines and cosines of u come from their Taylor series (error < 1e-10).
+struct HelixPt {
+    float x, y;          // position at s
+    float cm, sm;        // cos, sin of phi + u
+    float cp, sp;        // cos, sin of phi' = phi + 2u
+    float chord, S, dS;  // s sinc(u), sinc(u), d sinc/du
+    float u;
+};
+
+__device__ __forceinline__ void sinc_terms(float u, float& su, float& cu, float& S, float& dS) {
+    float au = fabsf(u);
+    if (au < 0.5f) {
+        float u2 = u * u;
+        S = 1.0f + u2 * (-1.0f / 6.0f + u2 * (1.0f / 120.0f + u2 * (-1.0f / 5040.0f + u2 * (1.0f / 362880.0f))));
+        cu = 1.0f + u2 * (-0.5f + u2 * (1.0f / 24.0f + u2 * (-1.0f / 720.0f + u2 * (1.0f / 40320.0f))));
+        dS = u * (-1.0f / 3.0f + u2 * (1.0f / 30.0f + u2 * (-1.0f / 840.0f + u2 * (1.0f / 45360.0f))));
+        su = u * S;
+    } else {
+        sincosf(u, &su, &cu);
+        float iu = 1.0f / u;
+        S = su * iu;
+        dS = (cu - S) * iu;
+    }
+}
+
+__device__ __forceinline__ void helix_at(float x, float y, float cphi, float sphi, float w, float s, HelixPt& h) {
+    float u = 0.5f * w * s;
+    float su, cu;
+    sinc_terms(u, su, cu, h.S, h.dS);
+    h.u = u;
+    h.chord = s * h.S;
+    h.cm = cphi * cu - sphi * su;
+    h.sm = sphi * cu + cphi * su;
+    h.x = fmaf(h.chord, h.cm, x);
+    h.y = fmaf(h.chord, h.sm, y);
+    h.cp = h.cm * cu - h.sm * su;
+    h.sp = h.sm * cu + h.cm * su;
+}
+
+// ------------------------------------------------------- cylinder crossing
+// Reachability of |xy| = R from (x, y) with heading phi and curvature w,
+// without dividing by w.  The track circle (centre distance d, radius rho)
+// meets the layer circle iff |R - rho| <= d <= R + rho; with
+// d^2 = r0^2 - 2 a'/w + rho^2, a' = x sin(phi) - y cos(phi), this reads
+//   |w| (R^2 - r0^2) <= 2 (R - sign(w) a')  and  |w| (r0^2 - R^2) <= 2 (R + sign(w) a'),
+// which at w = 0 reduces to the line's distance test |a'| <= R.
+__device__ __forceinline__ bool cylinder_reachable(float x, float y, float cphi, float sphi, float w, float R) {
+    float r0sq = fmaf(x, x, y * y);
+    float ap = x * sphi - y * cphi;
+    float sg = w >= 0.0f ? 1.0f : -1.0f;
+    float t = fabsf(w) * (R * R - r0sq);
+    return t <= 2.0f * (R - sg * ap) && -t <= 2.0f * (R + sg * ap);
+}
+
+// Straight-line path to |xy| = R (first positive root), or -1 if none.
+__device__ __forceinline__ float line_path(float x, float y, float cphi, float sphi, float R) {
+    float b = x * cphi + y * sphi;
+    float r0sq = fmaf(x, x, y * y);
+    float dr2 = R * R - r0sq;
+    float disc = fmaf(b, b, dr2);
+    if (disc < 0.0f) return -1.0f;
+    float sq = sqrtf(disc);
+    if (dr2 >= 0.0f) {  // outward: one positive root, cancellation-free form
+        float den = b + sq;
+        return den > 0.0f ? dr2 / den : -1.0f;
+    }
+    // inward: both roots positive when moving in (b < 0); the nearer one
+    return b < 0.0f ? dr2 / (b - sq) : -1.0f;
+}
+
+// Newton iteration on f(s) = (r(s)^2 - R^2) / (2R) (= r - R near the root)
+// from s0.  Stops when |f| <= tol; returns false after max_iter helix
+// evaluations without convergence.  h holds the last evaluation.
+__device__ __forceinline__ bool newton_cylinder(float x, float y, float cphi, float sphi, float w, float R,
+                                                float tol, int max_iter, float s0, float& s, HelixPt& h,
+                                                int& iters) {
+    const float inv2R = 0.5f / R;
+    const float invR = 1.0f / R;
+    s = s0;
+    for (int it = 0; it < max_iter; ++it) {
+        helix_at(x, y, cphi, sphi, w, s, h);
+        float f = (fmaf(h.x, h.x, h.y * h.y) - R * R) * inv2R;
+        iters = it + 1;
+        if (fabsf(f) <= tol) return true;
+        float fp = (h.x * h.cp + h.y * h.sp) * invR;
+        float ds = f / fp;
+        float sn = s - ds;
+        s = sn > 0.0f ? sn : 0.5f * s;   // keep the path positive
+    }
+    return false;
+}
+
+// -------------------------------------------------------- Jacobian blocks
+// Derivatives of the helix point at fixed s (omega = kq * ipt):
+//   dx'/domega = (s^2/2) (sinc'(u) cos phi_m - sinc(u) sin phi_m)
+//   dy'/domega = (s^2/2) (sinc'(u) sin phi_m + sinc(u) cos phi_m)
+//   dx'/dphi = -chord sin phi_m,  dy'/dphi = chord cos phi_m
+//   dphi'/domega = s,  dz'/dtheta = -s / sin^2 theta,  d(x', y', z', phi')/ds = (cos phi', sin phi', cot theta, omega)
+// The path s*(p) to the surface adds (d state/ds) (ds*/dp)^T, with
+// ds*/dp = -(dg/dp) / (dg/ds) for the surface constraint g(state(p, s)) = 0.
+struct Jac {
+    // rows x, y, phi: columns x, y, z, ipt, phi, theta (some are structurally 0)
+    float a[3][6];
+    // row z: columns x, y, z, ipt, phi, theta
+    float z[6];
+};
+
+// Cylinder: g = x'^2 + y'^2 - R^2, dg/ds = 2 D, D = x' cos phi' + y' sin phi'.
+// ds/dx = -x'/D, ds/dy = -y'/D, ds/dphi = -(x' y - x y')/D,
+// ds/dipt = -kq (x' dx'/domega + y' dy'/domega)/D, ds/dz = ds/dtheta = 0.
+__device__ __forceinline__ void jacobian_cylinder(float x, float y, float w, float kq, float s, float cot,
+                                                  float sinth, const HelixPt& h, Jac& J) {
+    float hs2 = 0.5f * s * s;
+    float dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
+    float dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
+    float iD = 1.0f / (h.x * h.cp + h.y * h.sp);
+    float dsx = -h.x * iD;
+    float dsy = -h.y * iD;
+    float dsphi = -(h.x * y - x * h.y) * iD;
+    float dsipt = -kq * (h.x * dxw + h.y * dyw) * iD;
+    // x' row
+    J.a[0][0] = fmaf(h.cp, dsx, 1.0f);
+    J.a[0][1] = h.cp * dsy;
+    J.a[0][2] = 0.0f;
+    J.a[0][3] = fmaf(h.cp, dsipt, kq * dxw);
+    J.a[0][4] = fmaf(h.cp, dsphi, -h.chord * h.sm);
+    J.a[0][5] = 0.0f;
+    // y' row
+    J.a[1][0] = h.sp * dsx;
+    J.a[1][1] = fmaf(h.sp, dsy, 1.0f);
+    J.a[1][2] = 0.0f;
+    J.a[1][3] = fmaf(h.sp, dsipt, kq * dyw);
+    J.a[1][4] = fmaf(h.sp, dsphi, h.chord * h.cm);
+    J.a[1][5] = 0.0f;
+    // phi' row
+    J.a[2][0] = w * dsx;
+    J.a[2][1] = w * dsy;
+    J.a[2][2] = 0.0f;
+    J.a[2][3] = fmaf(w, dsipt, kq * s);
+    J.a[2][4] = fmaf(w, dsphi, 1.0f);
+    J.a[2][5] = 0.0f;
+    // z' row
+    J.z[0] = cot * dsx;
+    J.z[1] = cot * dsy;
+    J.z[2] = 1.0f;
+    J.z[3] = cot * dsipt;
+    J.z[4] = cot * dsphi;
+    J.z[5] = -s / (sinth * sinth);
+}
+
+// Plane: g = z' - Z; ds/dz = -tan(theta), ds/dtheta = s / (sin cos), others 0.
+// The z' row vanishes (z' = Z).
+__device__ __forceinline__ void jacobian_plane(float w, float kq, float s, float tanth, float sinth, float costh,
+                                               const HelixPt& h, Jac& J) {
+    float hs2 = 0.5f * s * s;
+    float dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
+    float dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
+    float dsz = -tanth;
+    float dsth = s / (sinth * costh);
+    J.a[0][0] = 1.0f;  J.a[0][1] = 0.0f;  J.a[0][2] = h.cp * dsz;  J.a[0][3] = kq * dxw;
+    J.a[0][4] = -h.chord * h.sm;  J.a[0][5] = h.cp * dsth;
+    J.a[1][0] = 0.0f;  J.a[1][1] = 1.0f;  J.a[1][2] = h.sp * dsz;  J.a[1][3] = kq * dyw;
+    J.a[1][4] = h.chord * h.cm;   J.a[1][5] = h.sp * dsth;
+    J.a[2][0] = 0.0f;  J.a[2][1] = 0.0f;  J.a[2][2] = w * dsz;     J.a[2][3] = kq * s;
+    J.a[2][4] = 1.0f;  J.a[2][5] = w * dsth;
+    for (int k = 0; k < 6; ++k) J.z[k] = 0.0f;
+}
+
+// ------------------------------------------------- covariance transport
+// C' = J C J^T on the packed covariance.  Rows ipt and theta of J are unit
+// rows.  SURF 0 (cylinder): rows x, y, phi have non-zeros in columns
+// x, y, ipt, phi; row z in all columns (z coefficient 1).  SURF 1 (plane):
+// rows x, y, phi in all columns except (x: y), (y: x), (phi: x, y); row z = 0.
+// The structural zeros are skipped at compile time through the masks.
+template <int SURF>
+__device__ __forceinline__ void transport(const Jac& J, float* c) {
+    // column masks of the x, y, phi rows
+    constexpr unsigned MX = SURF == 0 ? 0b011011u : 0b111101u;   // bit k: column k used
+    constexpr unsigned MY = SURF == 0 ? 0b011011u : 0b111110u;
+    constexpr unsigned MP = SURF == 0 ? 0b011011u : 0b111100u;
+    // rows of M = J C for the transformed rows x(0), y(1), phi(4), z(2)
+    float M0[6], M1[6], M4[6], M2[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float m0 = 0.f, m1 = 0.f, m4 = 0.f;
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+            if (MX & (1u << l)) m0 = fmaf(J.a[0][l], c[I21(l, k)], m0);
+            if (MY & (1u << l)) m1 = fmaf(J.a[1][l], c[I21(l, k)], m1);
+            if (MP & (1u << l)) m4 = fmaf(J.a[2][l], c[I21(l, k)], m4);
+        }
+        M0[k] = m0; M1[k] = m1; M4[k] = m4;
+        if (SURF == 0) {
+            float m2 = c[I21(2, k)];
+#pragma unroll
+            for (int l = 0; l < 6; ++l)
+                if (l != 2) m2 = fmaf(J.z[l], c[I21(l, k)], m2);
+            M2[k] = m2;
+        }
+    }
+    // new rows: r(i) returns the row of M for transformed index i; rows 3, 5 are C's
+    auto Mrow = [&](int i, int k) -> float {
+        switch (i) {
+            case 0: return M0[k];
+            case 1: return M1[k];
+            case 2: return SURF == 0 ? M2[k] : 0.0f;
+            case 4: return M4[k];
+            default: return c[I21(i, k)];
+        }
+    };
+    auto dotJ = [&](int i, int j) -> float {   // (M J^T)_{ij} = sum_k M_ik J_jk
+        if (j == 3 || j == 5) return Mrow(i, j);
+        if (j == 2) {
+            if (SURF == 1) return 0.0f;
+            float a = Mrow(i, 2);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if (k != 2) a = fmaf(Mrow(i, k), J.z[k], a);
+            return a;
+        }
+        const unsigned m = j == 0 ? MX : (j == 1 ? MY : MP);
+        const int r = j == 0 ? 0 : (j == 1 ? 1 : 2);
+        float a = 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (m & (1u << k)) a = fmaf(Mrow(i, k), J.a[r][k], a);
+        return a;
+    };
+    float n[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) n[I21(i, j)] = dotJ(i, j);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c[k] = n[k];
+}
+
+// ----------------------------------------------------------- Kalman update
+// 3x3 symmetric inverse by cofactors, with the positive-definiteness test
+// on the leading minors (equivalent to Cholesky pivots d_k > tau S_kk):
+//   S00 > 0,  m2 = S00 S11 - S10^2 > tau S00 S11,  det > tau S22 m2.
+template <typename T>
+__device__ __forceinline__ bool inv3_spd(const T s[6], T inv[6], T tau) {
+    // s: packed (00, 10, 11, 20, 21, 22)
+    T c00 = s[2] * s[5] - s[4] * s[4];
+    T c10 = s[4] * s[3] - s[1] * s[5];
+    T c11 = s[0] * s[5] - s[3] * s[3];
+    T c20 = s[1] * s[4] - s[2] * s[3];
+    T c21 = s[3] * s[1] - s[0] * s[4];
+    T c22 = s[0] * s[2] - s[1] * s[1];
+    T det = s[0] * c00 + s[1] * c10 + s[3] * c20;
+    bool ok = (s[0] > T(0)) && (c22 > tau * s[0] * s[2]) && (det > tau * s[5] * c22);
+    if (!ok) return false;
+    T id = T(1) / det;
+    inv[0] = c00 * id; inv[1] = c10 * id; inv[2] = c11 * id;
+    inv[3] = c20 * id; inv[4] = c21 * id; inv[5] = c22 * id;
+    return true;
+}
+
+// Update of state st (already propagated to the surface) with hit m, V.
+//   S = C'_pos + V;  w = S^-1 r;  chi2 = r . w;  K = C' H^T S^-1 (6x3);
+//   p+ = p' + C' H^T w;
+//   C+ = A C' A^T + K V K^T,  A = I - K H   (Joseph form).
+// The Joseph form is evaluated as written: in FP32 its dominant term K V K^T
+// carries no cancellation, while A C' A^T is second order in the (small)
+// rows of A along the measured directions, so the posterior keeps close to
+// FP32 relative accuracy even when the update shrinks C' by orders of
+// magnitude.
+// Returns 0, or ST_S_NOT_PD / ST_CHI2_CUT when the update is skipped;
+// ST_FP64_FALLBACK is OR-ed into *flags when the FP64 inversion ran.
+__device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], const float V[6],
+                                                  const Params& P, float& chi2, uint32_t& flags) {
+    float* c = st.c;
+    float S[6] = {c[0] + V[0], c[1] + V[1], c[2] + V[2], c[3] + V[3], c[4] + V[4], c[5] + V[5]};
+    float Si[6];
+    if (P.fp64_fallback == 2 || !inv3_spd<float>(S, Si, PD_TAU32)) {
+        if (!P.fp64_fallback) return ST_S_NOT_PD;
+        double Sd[6], Sid[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Sd[k] = (double)c[k] + (double)V[k];
+        if (!inv3_spd<double>(Sd, Sid, PD_TAU64)) return ST_S_NOT_PD;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Si[k] = (float)Sid[k];
+        flags |= ST_FP64_FALLBACK;
+    }
+    float r0 = m[0] - st.p[0], r1 = m[1] - st.p[1], r2 = m[2] - st.p[2];
+    float w0 = Si[0] * r0 + Si[1] * r1 + Si[3] * r2;
+    float w1 = Si[1] * r0 + Si[2] * r1 + Si[4] * r2;
+    float w2 = Si[3] * r0 + Si[4] * r1 + Si[5] * r2;
+    float c2 = r0 * w0 + r1 * w1 + r2 * w2;
+    if (P.chi2_cut > 0.0f && c2 > P.chi2_cut) return ST_CHI2_CUT;
+    chi2 = c2;
+    // K = P S^-1 with P = C' H^T (rows c(i,0..2)); KV = K V
+    float K[6][3], KV[6][3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        float p0 = c[I21(i, 0)], p1 = c[I21(i, 1)], p2 = c[I21(i, 2)];
+        K[i][0] = p0 * Si[0] + p1 * Si[1] + p2 * Si[3];
+        K[i][1] = p0 * Si[1] + p1 * Si[2] + p2 * Si[4];
+        K[i][2] = p0 * Si[3] + p1 * Si[4] + p2 * Si[5];
+        KV[i][0] = K[i][0] * V[0] + K[i][1] * V[1] + K[i][2] * V[3];
+        KV[i][1] = K[i][0] * V[1] + K[i][1] * V[2] + K[i][2] * V[4];
+        KV[i][2] = K[i][0] * V[3] + K[i][1] * V[4] + K[i][2] * V[5];
+        st.p[i] = fmaf(p0, w0, fmaf(p1, w1, fmaf(p2, w2, st.p[i])));
+    }
+    // M = A C' (entries (i, l) with l <= i, and (i, j) with j < 3)
+    auto Mv = [&](int i, int l) -> float {
+        float a = c[I21(i, l)];
+        a = fmaf(-K[i][0], c[I21(0, l)], a);
+        a = fmaf(-K[i][1], c[I21(1, l)], a);
+        a = fmaf(-K[i][2], c[I21(2, l)], a);
+        return a;
+    };
+    float M[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int l = 0; l < 6; ++l)
+            if (l <= i || l < 3) M[i][l] = Mv(i, l);
+    // C+ = M A^T + K V K^T (lower triangle)
+    float n[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int l = 0; l <= i; ++l) {
+            float a = M[i][l];
+            a = fmaf(-M[i][0], K[l][0], a);
+            a = fmaf(-M[i][1], K[l][1], a);
+            a = fmaf(-M[i][2], K[l][2], a);
+            float q = KV[i][0] * K[l][0];
+            q = fmaf(KV[i][1], K[l][1], q);
+            q = fmaf(KV[i][2], K[l][2], q);
+            n[I21(i, l)] = a + q;
+        }
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c[k] = n[k];
+    return 0;
+}
+
+__device__ __forceinline__ float wrap_phi(float a) {
+    float r = a - TWO_PI_F * floorf((a + PI_F) * INV_TWO_PI_F);
+    return r <= -PI_F ? r + TWO_PI_F : (r > PI_F ? r - TWO_PI_F : r);
+}
+
+__device__ __forceinline__ bool finite3(const float m[3]) {
+    return isfinite(m[0]) && isfinite(m[1]) && isfinite(m[2]);
+}
+
+__device__ __forceinline__ bool bad_input(const State& st) {
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) bad |= !isfinite(st.p[i]);
+#pragma unroll
+    for (int i = 0; i < 21; ++i) bad |= !isfinite(st.c[i]);
+    bad |= !(st.p[3] > 0.0f);
+    bad |= !(st.p[5] > 0.0f && st.p[5] < PI_F);
+    return bad;
+}
+
+// --------------------------------------------------------- one layer step
+// Cylinder of radius R.  Returns the status flags of the layer; on success
+// the state is updated and *updated set.
+struct StepOut {
+    uint32_t flags;
+    bool updated;
+    int iters;
+};
+
+__device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float m[3], const float V[6],
+                                                 const Params& P, float& chi2, float tol, float s_start) {
+    StepOut o{0u, false, 0};
+    if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
+    float x = st.p[0], y = st.p[1];
+    float sphi, cphi;
+    sincosf(st.p[4], &sphi, &cphi);
+    float kq = -st.q * KAPPA * P.bz;
+    float w = kq * st.p[3];
+    if (!cylinder_reachable(x, y, cphi, sphi, w, R)) { o.flags = ST_NO_CROSSING; return o; }
+    float s0 = s_start > 0.0f ? s_start : line_path(x, y, cphi, sphi, R);
+    if (!(s0 > 0.0f)) s0 = fabsf(R - sqrtf(fmaf(x, x, y * y)));
+    HelixPt h;
+    float s;
+    if (!newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, s0, s, h, o.iters)) {
+        o.flags = ST_NEWTON_FAIL;
+        return o;
+    }
+    float sinth, costh;
+    sincosf(st.p[5], &sinth, &costh);
+    float cot = costh / sinth;
+    Jac J;
+    jacobian_cylinder(x, y, w, kq, s, cot, sinth, h, J);
+    st.p[0] = h.x;
+    st.p[1] = h.y;
+    st.p[2] = fmaf(s, cot, st.p[2]);
+    st.p[4] = st.p[4] + 2.0f * h.u;
+    transport<0>(J, st.c);
+    uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
+    o.flags |= u;
+    o.updated = (u == 0);
+    st.p[4] = wrap_phi(st.p[4]);
+    return o;
+}
+
+// Plane z = Z.
+__device__ __forceinline__ StepOut step_plane(State& st, float Z, const float m[3], const float V[6],
+                                              const Params& P, float& chi2) {
+    StepOut o{0u, false, 0};
+    if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
+    float sinth, costh;
+    sincosf(st.p[5], &sinth, &costh);
+    float tanth = sinth / costh;
+    float s = (Z - st.p[2]) * tanth;
+    if (!(s > 0.0f)) { o.flags = ST_NO_CROSSING; return o; }
+    float sphi, cphi;
+    sincosf(st.p[4], &sphi, &cphi);
+    float kq = -st.q * KAPPA * P.bz;
+    float w = kq * st.p[3];
+    HelixPt h;
+    helix_at(st.p[0], st.p[1], cphi, sphi, w, s, h);
+    Jac J;
+    jacobian_plane(w, kq, s, tanth, sinth, costh, h, J);
+    st.p[0] = h.x;
+    st.p[1] = h.y;
+    st.p[2] = Z;
+    st.p[4] = st.p[4] + 2.0f * h.u;
+    transport<1>(J, st.c);
+    uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
+    o.flags |= u;
+    o.updated = (u == 0);
+    st.p[4] = wrap_phi(st.p[4]);
+    return o;
+}
+
+// Newton tolerance for a cylinder of radius R: max(tol, 2 ulp(R)).
+__device__ __forceinline__ float newton_tol(float tol, float R) {
+    float ulp = __int_as_float(__float_as_int(fabsf(R)) & 0x7f800000) * 1.1920928955078125e-7f;
+    return fmaxf(tol, 2.0f * ulp);
+}
+
+}  // namespace p2r

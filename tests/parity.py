@@ -1,0 +1,84 @@
+"""Element-by-element comparison of GPU fit outputs with the FP64 oracle.
+
+Tolerances (FP32 GPU against FP64 oracle on the same FP32-rounded inputs):
+  parameters: |d| <= 1e-4 max(|ref|, f), f = 1 cm for x, y, z, 1 rad for
+              phi (compared modulo 2 pi), 0 for 1/pT and theta;
+  chi2:       |d| <= 1e-3 max(ref, 1);
+  covariance: element (i, j) passes when |d| <= 1e-3 |ref| or
+              |d| / sqrt(ref_ii ref_jj) <= 1e-5 (elements that vanish in
+              exact arithmetic, such as those along the surface normal, are
+              judged relative to the diagonal scale; diagonals are floored at
+              1e-12 of the largest position variance, for rows that vanish
+              identically such as z after a plane);
+  status:     flags bit-exact except FP64_FALLBACK (GPU only); the count of
+              applied updates exact.
+Tracks whose reachability of a surface differs between FP32 and FP64 (the
+surface grazes the track's largest radius) are listed and excluded from the
+value comparison; their number must stay below 1e-4 of the tracks.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PAR_F = np.array([1.0, 1.0, 1.0, 0.0, 1.0, 0.0])
+IL = np.tril_indices(6)
+ST_FP64_FALLBACK = 1 << 2
+ST_NO_CROSSING = 1 << 0
+ST_NEWTON_FAIL = 1 << 1
+
+
+def compare(gpu: dict, ref: dict, max_excluded_frac: float = 1e-4, ctx: str = "") -> dict:
+    """gpu/ref dicts with par (n,6), cov (n,21), chi2 (n,), status (n,) [ref: + nused]."""
+    gp, rp = np.asarray(gpu["par"], np.float64), np.asarray(ref["par"], np.float64)
+    gc, rc = np.asarray(gpu["cov"], np.float64), np.asarray(ref["cov"], np.float64)
+    gx, rx = np.asarray(gpu["chi2"], np.float64), np.asarray(ref["chi2"], np.float64)
+    gs = np.asarray(gpu["status"]).astype(np.int64) & 0xFFFFFFFF
+    rs = (np.asarray(ref["status"]).astype(np.int64) & 0xFFFFFFFF) | (np.asarray(ref["nused"]).astype(np.int64) << 8)
+    n = gp.shape[0]
+    flags_g = gs & ~np.int64(ST_FP64_FALLBACK)
+    flags_r = rs
+    geo = np.int64(ST_NO_CROSSING | ST_NEWTON_FAIL)
+    # reachability disagreements near tangency
+    excl = ((flags_g & geo) != (flags_r & geo))
+    n_excl = int(excl.sum())
+    assert n_excl <= max(1, int(max_excluded_frac * n)), f"{ctx}: {n_excl} reachability disagreements"
+    keep = ~excl
+    bad_status = np.nonzero(keep & (flags_g != flags_r))[0]
+    assert bad_status.size == 0, f"{ctx}: status mismatch at {bad_status[:10]}: gpu {gs[bad_status[:5]]} ref {rs[bad_status[:5]]}"
+    d = gp - rp
+    d[:, 4] = np.angle(np.exp(1j * d[:, 4]))
+    d[np.isnan(gp) & np.isnan(rp)] = 0.0       # passed-through NaN of a rejected input
+    tolp = 1e-4 * np.maximum(np.abs(rp), PAR_F)
+    okp = np.abs(d) <= tolp
+    okp[~keep] = True
+    assert okp.all(), _worst(f"{ctx}: params", d, tolp, okp)
+    dx = np.abs(gx - rx)
+    tolx = 1e-3 * np.maximum(rx, 1.0)
+    okx = (dx <= tolx) | ~keep
+    assert okx.all(), _worst(f"{ctx}: chi2", dx[:, None], tolx[:, None], okx[:, None])
+    dc = np.abs(gc - rc)
+    dc[np.isnan(gc) & np.isnan(rc)] = 0.0
+    diag = np.abs(rc[:, [0, 2, 5, 9, 14, 20]])
+    # a row that vanishes in exact arithmetic (z after a plane: z' = Z) has an
+    # oracle diagonal at rounding level; floor it at 1e-12 of the position block
+    diag = np.maximum(diag, 1e-12 * diag[:, :3].max(1, keepdims=True))
+    scale = np.sqrt(diag[:, IL[0]] * diag[:, IL[1]])
+    ok_rel = dc <= 1e-3 * np.abs(rc)
+    ok_norm = dc <= 1e-5 * scale
+    okc = ok_rel | ok_norm
+    okc[~keep] = True
+    assert okc.all(), _worst(f"{ctx}: cov", dc, np.maximum(1e-3 * np.abs(rc), 1e-5 * scale), okc)
+    relp = np.abs(d) / np.maximum(np.abs(rp), np.maximum(PAR_F, 1e-30))
+    normerr = np.where(keep[:, None], dc / np.maximum(scale, 1e-300), 0.0)
+    return dict(n=n, excluded=n_excl, cov_norm_err_max=float(normerr.max()),
+                cov_norm_err_p999=float(np.quantile(normerr, 0.999)), max_rel_par=relp[keep].max(0) if keep.any() else np.zeros(6),
+                max_rel_chi2=float((dx / np.maximum(rx, 1.0))[keep].max()) if keep.any() else 0.0,
+                cov_rel_pass=int(ok_rel[keep].sum()), cov_norm_only=int((ok_norm & ~ok_rel)[keep].sum()),
+                fp64_fallbacks=int(((gs & ST_FP64_FALLBACK) != 0).sum()))
+
+
+def _worst(what, d, tol, ok):
+    bad = np.argwhere(~ok)
+    r = (np.abs(d) / np.maximum(tol, 1e-300))
+    i = np.unravel_index(np.argmax(np.where(ok, 0, r)), r.shape)
+    return f"{what}: {bad.shape[0]} failures; worst at {i}: |d|={np.abs(d)[i]:.3e} tol={tol[i]:.3e}"

@@ -1,0 +1,222 @@
+"""GPU parity of the p2r and p2z fits against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2401_14221_amd as p2r
+from synth import events as ev
+
+from .parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = p2r.Context(0)
+    yield c
+    c.close()
+
+
+def run_p2r(ctx, d, W, **kw):
+    dev = "cuda"
+    n = d["par"].shape[0]
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device=dev)
+    hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device=dev)
+    radii = torch.as_tensor(d["surf"], dtype=torch.float32, device=dev)
+    out, chi2, st = ctx.p2r_propagate_update(n, radii, trk, hits, width=W, **kw)
+    torch.cuda.synchronize()
+    par, cov, q = p2r.unpack_tracks(out, n)
+    return dict(par=par.cpu().numpy(), cov=cov.cpu().numpy(), chi2=chi2.cpu().numpy(),
+                status=st.cpu().numpy().view(np.uint32), q=q.cpu().numpy())
+
+
+def run_p2z(ctx, d, **kw):
+    dev = "cuda"
+    n = d["par"].shape[0]
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64, device=dev)
+    hits = p2r.pack_hits_p2z(d["hits"], d["hitcov"], device=dev)
+    zs = torch.as_tensor(d["surf"], dtype=torch.float32, device=dev)
+    out, chi2, st = ctx.p2z_propagate_update(n, zs, trk, hits, **kw)
+    torch.cuda.synchronize()
+    par, cov, q = p2r.unpack_tracks(out, n)
+    return dict(par=par.cpu().numpy(), cov=cov.cpu().numpy(), chi2=chi2.cpu().numpy(),
+                status=st.cpu().numpy().view(np.uint32), q=q.cpu().numpy())
+
+
+def _sub(d, idx):
+    out = dict(d)
+    for k in ("par", "cov", "q", "hits", "hitcov", "truth", "truth_start", "path"):
+        out[k] = d[k][idx]
+    return out
+
+
+@pytest.mark.parametrize("W", [32, 64, 128, 256])
+def test_p2r_parity_1024x10(ctx, W):
+    d = ev.make_barrel_event(ev.P2R_PARITY)
+    g = run_p2r(ctx, d, W)
+    r = oracle.fit_event(d, "barrel")
+    rep = compare(g, r, ctx=f"p2r W={W}")
+    print(f"W={W}", rep, flush=True)
+    assert np.all(g["q"] == d["q"])
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 1000, 4099])
+def test_p2r_ragged_tail(ctx, n):
+    d = ev.make_barrel_event(ev.P2R_THROUGHPUT.with_(seed=77), n_tracks=n)
+    for W in (64, 256):
+        g = run_p2r(ctx, d, W)
+        r = oracle.fit_event(d, "barrel")
+        compare(g, r, ctx=f"p2r n={n} W={W}")
+
+
+def test_p2r_tail_lanes_untouched(ctx):
+    """Lanes past n in the last block are neither read nor written."""
+    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=70)
+    W = 64
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device="cuda")
+    trk.view(-1, 28, W)[1, :, 6:] = float("nan")      # garbage in the tail of block 1
+    hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device="cuda")
+    radii = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
+    out = torch.full_like(trk, 12345.0)
+    chi2 = torch.full((70,), -1.0, device="cuda")
+    st = torch.zeros(70, dtype=torch.int32, device="cuda")
+    ctx.p2r_propagate_update(70, radii, trk, hits, out=(out, chi2, st), width=W)
+    torch.cuda.synchronize()
+    assert torch.all(out.view(-1, 28, W)[1, :, 6:] == 12345.0)
+    assert torch.all(torch.isfinite(out.view(-1, 28, W)[1, :, :6]))
+
+
+def test_p2z_parity(ctx):
+    d = ev.make_disk_event(ev.P2Z_THROUGHPUT, n_tracks=3000)
+    g = run_p2z(ctx, d)
+    r = oracle.fit_event(d, "disk")
+    rep = compare(g, r, ctx="p2z")
+    print("p2z", rep, flush=True)
+
+
+def test_p2r_full_size_sampled(ctx):
+    """100 x 9600 x 20 in the launch configuration the benchmark uses; sampled tracks vs the oracle."""
+    d = ev.make_barrel_event(ev.P2R_THROUGHPUT)
+    n = d["par"].shape[0]
+    W = ctx.layout_width(0)
+    g = run_p2r(ctx, d, W)
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([rng.choice(n, 6000, replace=False), np.arange(64), np.arange(n - 64, n)]))
+    r = oracle.fit_event(_sub(d, idx), "barrel")
+    gs = {k: v[idx] for k, v in g.items()}
+    rep = compare(gs, r, ctx="p2r full")
+    print("p2r full sampled", rep, flush=True)
+    # properties of every track
+    st = g["status"]
+    assert np.all(st & p2r.ST_DONE)
+    assert np.all(np.isfinite(g["par"])) and np.all(np.isfinite(g["chi2"]))
+    full = ((st >> 8) & 0xFF) == 20
+    assert full.mean() > 0.97
+    assert g["chi2"][full].mean() / 60.0 == pytest.approx(1.0, abs=0.02)
+
+
+def test_p2z_full_size_sampled(ctx):
+    d = ev.make_disk_event(ev.P2Z_THROUGHPUT)
+    n = d["par"].shape[0]
+    g = run_p2z(ctx, d)
+    rng = np.random.default_rng(1)
+    idx = np.unique(np.concatenate([rng.choice(n, 6000, replace=False), np.arange(n - 64, n)]))
+    r = oracle.fit_event(_sub(d, idx), "disk")
+    rep = compare({k: v[idx] for k, v in g.items()}, r, ctx="p2z full")
+    print("p2z full sampled", rep, flush=True)
+    assert np.all(g["status"] & p2r.ST_DONE)
+
+
+def test_edge_cases_status(ctx):
+    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=8)
+    par, cov, hits, hc = d["par"].copy(), d["cov"].copy(), d["hits"].copy(), d["hitcov"].copy()
+    par[0, 3] = 1 / 0.3
+    cov[0, 9] = 1e-14                 # 1/pT fixed: outer layers unreachable
+    par[1, 0] = np.nan                # bad input
+    hits[2, 3] = np.nan               # missing hit
+    par[3, 5] = -0.1                  # theta out of range
+    hc[4, :, :] = 0.0                 # V = 0: S singular along the normal
+    hits[5, 4, 0] += 5.0              # an outlier for the chi2 cut
+    e = dict(d, par=par, cov=cov, hits=hits, hitcov=hc)
+    g = run_p2r(ctx, e, 64, chi2_cut=200.0)
+    r = oracle.fit_event(e, "barrel", chi2_cut=200.0)
+    compare(g, r, ctx="edge")
+    st = g["status"]
+    assert st[0] & p2r.ST_NO_CROSSING
+    assert st[1] & p2r.ST_BAD_INPUT and st[3] & p2r.ST_BAD_INPUT
+    assert st[2] & p2r.ST_HIT_MISSING
+    assert st[4] & p2r.ST_S_NOT_PD
+    assert st[5] & p2r.ST_CHI2_CUT
+    assert np.all(g["par"][1, 1:] == d["par"][1, 1:].astype(np.float32))
+
+
+def test_fp64_inversion_forced_matches(ctx):
+    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=512)
+    g = run_p2r(ctx, d, 64, fp64_fallback=2)
+    r = oracle.fit_event(d, "barrel")
+    compare(g, r, ctx="forced fp64")
+    assert np.all(g["status"] & p2r.ST_FP64_FALLBACK)
+
+
+def test_fp64_fallback_triggers_on_ill_conditioned_S(ctx):
+    """A hit 1e-4 as wide radially as tangentially makes the FP32 test fail and the FP64 inversion run."""
+    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=64)
+    hc = d["hitcov"].copy()
+    hc[:, 5, 0] = hc[:, 5, 2] = 2e-9    # x, y variance of layer 5 tiny; z unchanged
+    e = dict(d, hitcov=hc)
+    g = run_p2r(ctx, e, 64)
+    r = oracle.fit_event(e, "barrel")
+    st = g["status"]
+    assert (st & p2r.ST_FP64_FALLBACK).mean() > 0.5
+    assert np.all(np.isfinite(g["par"]))
+    # FP32 arithmetic around an S with condition ~1e6: agreement at 1e-3 of the parameters
+    dpar = np.abs(g["par"] - r["par"])
+    dpar[:, 4] = np.abs(np.angle(np.exp(1j * (g["par"][:, 4] - r["par"][:, 4]))))
+    assert np.all(dpar <= 1e-3 * np.maximum(np.abs(r["par"]), [1, 1, 1, 0, 1, 0]) + 1e-6)
+
+
+def test_empty_and_argument_errors(ctx):
+    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=10)
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64, device="cuda")
+    hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], 64, device="cuda")
+    radii = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
+    ctx.p2r_propagate_update(0, radii, trk, hits, width=64)    # n = 0: nothing to do
+    with pytest.raises(p2r.P2RError) as e:
+        ctx.p2r_propagate_update(10, radii, trk, hits, width=48)
+    assert e.value.code == p2r.P2R_ELAYOUT
+    with pytest.raises(p2r.P2RError) as e:
+        ctx.p2r_propagate_update(10, radii, trk, hits, width=64, newton_max_iter=0)
+    assert e.value.code == p2r.P2R_EINVAL
+    with pytest.raises(p2r.P2RError) as e:
+        ctx.p2z_propagate_update(10, radii, trk, hits, width=32)
+    assert e.value.code == p2r.P2R_ELAYOUT
+    with pytest.raises(p2r.P2RError) as e:
+        _misaligned(ctx, radii, trk, hits)
+    assert e.value.code == p2r.P2R_ELAYOUT
+
+
+def _misaligned(ctx, radii, trk, hits):
+    import ctypes as C
+    from paper_2401_14221_amd import _lib
+    buf = torch.empty(trk.numel() + 1, dtype=torch.float32, device="cuda")
+    o = _lib.default_opts(width=64)
+    out = C.c_void_p(buf.data_ptr() + 2)
+    rc = _lib.library().p2r_propagate_update(ctx._h, C.byref(o), 10, radii.numel(), C.c_void_p(radii.data_ptr()),
+                                             C.c_void_p(trk.data_ptr()), C.c_void_p(hits.data_ptr()), out,
+                                             C.c_void_p(buf.data_ptr()), C.c_void_p(buf.data_ptr()), None)
+    _lib._check(rc)
+
+
+def test_autotune_picks_a_variant(ctx, tmp_path):
+    c = p2r.Context(0, tune_cache=str(tmp_path / "tune.json"))
+    c.autotune(0, 96000, 20)
+    W = c.layout_width(0)
+    assert W in (32, 64, 128, 256)
+    assert (tmp_path / "tune.json").exists()
+    c2 = p2r.Context(0, tune_cache=str(tmp_path / "tune.json"))
+    c2.autotune(0, 96000, 20)                 # served from the cache
+    assert c2.variant_name(0) == c.variant_name(0)
+    c.autotune(1, 32768, 20)
+    assert c.layout_width(1) == 64
