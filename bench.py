@@ -181,7 +181,90 @@ def extra_legs(ctx, args, stream, ev, p2r, dev):
                                      "note": "pinned host buffers, H2D + fit + D2H on one stream"}}
     log(f"p2z: {ms:.3f} ms/step; with transfers {ms_x:.3f} ms")
     del trk, hits, o
+
+    # ragged batched fit, 1,000,000 tracks with 5..25 mixed surfaces, one graph launch per step
+    cfg = ev.RAGGED
+    log(f"generating {cfg.name}")
+    d = ev.make_ragged_event(cfg)
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    off = torch.as_tensor(d["offsets"], dtype=torch.int64, device=dev)
+    stype = torch.as_tensor(d["surf_type"], dtype=torch.uint8, device=dev)
+    sval, hpos, hcov = f(d["surf_val"]), f(d["hits"]), f(d["hitcov"])
+    par, cov = f(d["par"]), f(d["cov"])
+    q = torch.as_tensor(d["q"], dtype=torch.int8, device=dev)
+    n = par.shape[0]
+    H = int(d["offsets"][-1])
+    ro = (torch.empty((n, 6), device=dev), torch.empty((n, 21), device=dev), torch.empty(n, device=dev),
+          torch.empty(n, dtype=torch.int32, device=dev))
+    ropts = p2r._lib.default_opts(chi2_cut=30.0)      # outliers up to ~100 sigma: per-hit chi2 cut
+    lmax = cfg.extra["lmax"]
+
+    def rstep():
+        ctx.fit_tracks_batched(off, stype, sval, hpos, hcov, par, cov, q, H, lmax, out=ro, opts=ropts,
+                               stream=stream)
+
+    ms_r, _ = timed(rstep, args.steps, args.warmup, stream)
+    alg_r = n * (TRACK_BYTES + 8) + H * (HIT_BYTES + 5)
+    out["ragged"] = {"workload": cfg.name, "ms_per_step": ms_r, "value": H / (ms_r * 1e-3), "unit": UNIT,
+                     "track_layers": H, "hbm_frac": alg_r / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                     "variant": ctx.variant_name(2), "note": "one HIP graph per step: sort + persistent fit"}
+    log(f"ragged: {ms_r:.3f} ms/step, {H / (ms_r * 1e-3):.3e} track-layers/s")
+    del off, stype, sval, hpos, hcov, par, cov, q, ro
+    out["learned"] = learned_leg(ctx, args, stream, ev, p2r, dev)
     return out
+
+
+def learned_leg(ctx, args, stream, ev, p2r, dev):
+    """Learned vs plain start on the 100 x 9600 x 20 evaluation workload (same GPU, same tolerance)."""
+    import torch
+    from paper_2401_14221_amd import learned
+    if not os.path.exists(learned.DEFAULT_CKPT):
+        return {"skipped": "no trained network (paper_2401_14221_amd/data/mlp_p2r.ckpt)"}
+    mlp = p2r.Mlp(ctx)
+    mlp.load(learned.DEFAULT_CKPT)
+    cfg = ev.LEARNED_EVAL
+    L = len(cfg.surfaces)
+    n = cfg.n_total
+    W = ctx.layout_width(0)
+    log(f"generating {cfg.name}")
+    d = ev.make_barrel_event(cfg)
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device=dev)
+    hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device=dev)
+    radii = torch.as_tensor(d["surf"], dtype=torch.float32, device=dev)
+    res = {"workload": cfg.name}
+    outs = {}
+    for name, m in (("plain", None), ("learned", mlp)):
+        o = (torch.empty_like(trk), torch.empty(n, dtype=torch.float32, device=dev),
+             torch.empty(n, dtype=torch.int32, device=dev))
+        opts = p2r._lib.default_opts(width=W)
+        if m is not None:
+            opts.mlp = m.handle.value
+
+        def step():
+            ctx.p2r_propagate_update(n, radii, trk, hits, out=o, opts=opts, stream=stream)
+
+        ms, _ = timed(step, args.steps, args.warmup, stream)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        opts.helix_evals = cnt.data_ptr()
+        step()
+        torch.cuda.synchronize()
+        st = o[2].cpu().numpy().view(np.uint32)
+        res[name] = {"ms_per_step": ms, "value": n * L / (ms * 1e-3), "unit": UNIT,
+                     "helix_evals_per_track_layer": float(cnt.item()) / (n * L),
+                     "ml_rejected_tracks": int(((st & p2r.ST_ML_REJECTED) != 0).sum())}
+        outs[name] = o
+    par_p, _, _ = p2r.unpack_tracks(outs["plain"][0], n)
+    par_l, _, _ = p2r.unpack_tracks(outs["learned"][0], n)
+    dphi = torch.remainder(par_l[:, 4] - par_p[:, 4] + np.pi, 2 * np.pi) - np.pi
+    dpar = (par_l - par_p).abs()
+    dpar[:, 4] = dphi.abs()
+    scale = torch.maximum(par_p.abs(), torch.tensor([1, 1, 1, 0, 1, 0], dtype=torch.float32, device=dev))
+    res["max_rel_diff_learned_vs_plain"] = float((dpar / scale.clamp_min(1e-30)).max())
+    res["speed_ratio_learned_over_plain"] = res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"]
+    log(f"learned: {res['learned']['ms_per_step']:.3f} ms vs plain {res['plain']['ms_per_step']:.3f} ms; "
+        f"evals/track-layer {res['learned']['helix_evals_per_track_layer']:.3f} vs "
+        f"{res['plain']['helix_evals_per_track_layer']:.3f}")
+    return res
 
 
 def cpu_baseline(d, ev):

@@ -7,8 +7,8 @@
  * surface in a uniform field B z-hat, transport the 6x6 covariance with the
  * Jacobian (C' = J C J^T), and Kalman-update with the surface's 3D hit
  * (innovation covariance S, gain, state and Joseph-form covariance update,
- * chi2).  One GPU lane handles one track; the arithmetic is FP32 with an FP64
- * 3x3 inversion when the FP32 positive-definiteness test of S fails.
+ * chi2).  One GPU lane handles one track; the arithmetic is FP32, with the
+ * update taken to FP64 when the FP32 positive-definiteness test of S fails.
  *
  * Units: cm, GeV, tesla, radians.  Curvature omega = -q * 2.99792458e-3 * B / pT
  * [1/cm]; positive tracks turn clockwise seen from +z.  Path lengths are
@@ -70,17 +70,23 @@ extern "C" {
 typedef struct p2r_ctx p2r_ctx; /* opaque: device, tuned variants, workspace, graphs */
 
 /* Fit options.  p2r_opts_default() fills: bz 3.8 T, newton_tol 1e-6 cm,
- * 8 iterations, chi2 cut off, FP64 fallback on, width 0 (tuned/default),
- * no MLP. */
+ * 8 iterations, chi2 cut off, FP64 fallback 3, width 0 (tuned/default),
+ * no MLP, graphs on. */
 typedef struct {
     float bz_tesla;          /* field along +z */
     float newton_tol_cm;     /* |r(s) - R| tolerance, raised to 2 ulp(R) */
     int32_t newton_max_iter; /* helix evaluations before NEWTON_FAIL */
     float chi2_cut;          /* <= 0: off; else skip updates with chi2 > cut */
-    int32_t fp64_fallback;   /* 1: FP64 inversion when the FP32 PD test fails; 0: skip the update
-                                instead; 2: always invert S in FP64 (testing) */
+    int32_t fp64_fallback;   /* when the FP32 PD test of S fails: 3 = the whole update (inverse,
+                                gain, Joseph covariance) in FP64; 1 = only the 3x3 inverse in
+                                FP64; 0 = skip the update; 2 = the FP64 update for every
+                                surface (testing) */
     int32_t width;           /* AoSoA width for p2r: 0 = context's tuned width, or 32/64/128/256 */
     const void* mlp;         /* NULL: plain start; else a p2r_mlp handle (learned start, p2r only) */
+    int32_t use_graph;       /* fit_tracks_batched: 1 = capture once per shape and replay a HIP
+                                graph (needs a non-NULL stream); 0 = launch the kernels directly */
+    unsigned long long* helix_evals; /* nullable device counter: p2r adds the number of helix
+                                evaluations of its cylinder solves (diagnostics) */
 } p2r_opts;
 
 void p2r_opts_default(p2r_opts* o);
@@ -119,32 +125,75 @@ int p2z_propagate_update(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, i
                          const float* layer_z, const float* trk_in, const float* hits,
                          float* trk_out, float* chi2_out, uint32_t* status, void* stream);
 
-/* Ragged batched fit: every track has its own ordered list of surfaces
- * (CSR), each a cylinder (surf_type 0, surf_val = radius) or a plane
- * (surf_type 1, surf_val = signed z), and one 3D hit per surface.
- *   offsets [n_tracks+1] (int64, offsets[0] = 0), surf_type [H] (uint8),
- *   surf_val [H], hit_pos [H][3], hit_cov [H][6] (packed), par_in [n][6],
- *   cov_in [n][21], q [n] (int8 +-1); outputs par_out [n][6],
- *   cov_out [n][21], chi2_out [n], status [n].
- * Tracks are packed (sorted by surface count) into the AoSoA layout by a
- * device kernel and fitted by one persistent kernel that takes blocks of
- * tracks from an atomic work queue; the three steps run as one HIP graph,
- * captured on the first call for a given (n_tracks, total surfaces) and
- * replayed afterwards.  The packing workspace lives in the context and is
- * reused: calls on one context must not overlap. */
-int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, const int64_t* offsets,
-                       const uint8_t* surf_type, const float* surf_val, const float* hit_pos,
-                       const float* hit_cov, const float* par_in, const float* cov_in, const int8_t* q,
-                       float* par_out, float* cov_out, float* chi2_out, uint32_t* status, void* stream);
+/* Ragged batched fit (paper Section 2's per-track layer loop with per-track
+ * layer lists): every track has its own ordered list of surfaces (CSR),
+ * each a cylinder (surf_type 0, surf_val = radius) or a plane (surf_type 1,
+ * surf_val = signed z), and one 3D hit per surface.
+ *   n_tracks tracks, n_hits = offsets[n_tracks] surfaces in total (host
+ *   value, used to check sizes), max_surfaces >= every track's count
+ *   (<= 255; a track with more, or a negative count, is BAD_INPUT).
+ *   offsets [n_tracks+1] (int64, offsets[0] = 0), surf_type [n_hits] (uint8),
+ *   surf_val [n_hits], hit_pos [n_hits][3], hit_cov [n_hits][6] (packed),
+ *   par_in [n][6], cov_in [n][21], q [n] (int8 +-1); outputs par_out [n][6],
+ *   cov_out [n][21], chi2_out [n], status [n].  A surf_type other than 0/1
+ *   skips that surface and sets BAD_INPUT.
+ * The tracks are counting-sorted on the device by (surface count, |eta|
+ * bin) and fitted by one persistent kernel whose waves take blocks of 64
+ * sorted tracks from an atomic counter; the five kernels run as one HIP
+ * graph, captured on the first call for a given set of arguments and
+ * replayed afterwards (opts->use_graph, non-NULL stream).  The sort
+ * workspace lives in the context (allocated on first use, grown when
+ * needed): calls on one context must not overlap. */
+int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits,
+                       int32_t max_surfaces, const int64_t* offsets, const uint8_t* surf_type,
+                       const float* surf_val, const float* hit_pos, const float* hit_cov,
+                       const float* par_in, const float* cov_in, const int8_t* q, float* par_out,
+                       float* cov_out, float* chi2_out, uint32_t* status, void* stream);
 
-/* Autotune `which` (0 p2r, 1 p2z, 2 ragged) on synthetic tracks of this
- * shape: times every compiled variant (width, waves per SIMD, layer-loop
- * unroll) with HIP events, keeps the fastest in the context and writes the
- * cache file if the context has one.  Synchronises the stream. */
+/* Autotune `which` (0 p2r, 1 p2z) on synthetic tracks of this shape: times
+ * every compiled variant (width, waves per SIMD, layer-loop unroll) with HIP
+ * events, keeps the fastest in the context and writes the cache file if the
+ * context has one.  Allocates and frees temporary device buffers;
+ * synchronises the stream. */
 int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, void* stream);
 
 /* Description of the variant in use for `which` (host string owned by ctx). */
 const char* p2r_variant_name(p2r_ctx* ctx, int which);
+
+/* ---------------------------------------------------------------------
+ * Learned path-length proposal (not in the paper; the north-star
+ * extension): an MLP 7 -> 64 -> 64 -> 1 with ReLU, BF16 weights on the
+ * matrix cores and FP32 accumulation, that proposes the starting path length
+ * of the helix-to-cylinder Newton iteration.  Input: 7 features of the state
+ * and the target radius R (p2r_mlp_features); output y with the proposal
+ * s0 = s_line (1 + y / 100), s_line the straight-line path.  The iteration
+ * refines s0, and rejects it (ML_REJECTED, plain start) when |r(s0) - R| >
+ * 1e-3 cm.  Parameters: one flat FP32 vector of p2r_mlp_n_params() = 4737
+ * values, W1 [64][7], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 [1]
+ * (row-major, y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3).
+ * Pass the handle as p2r_opts.mlp to p2r_propagate_update for the learned
+ * start.  Buffers are device pointers unless stated. */
+typedef struct p2r_mlp p2r_mlp;
+int p2r_mlp_create(p2r_ctx* ctx, p2r_mlp** out);        /* allocates master weights, Adam state */
+void p2r_mlp_destroy(p2r_mlp* mlp);
+int p2r_mlp_n_params(void);
+/* host_params: host array of p2r_mlp_n_params() floats; resets Adam; synchronises. */
+int p2r_mlp_set_params(p2r_mlp* mlp, const float* host_params);
+int p2r_mlp_get_params(p2r_mlp* mlp, float* host_params);
+/* Features x [n][7] (and, with s_label [n], targets t [n] = 100 (s_label / s_line - 1);
+ * s_line [n] nullable) of states par [n][6], charges q [n] (+-1.0f) and radii R [n]. */
+int p2r_mlp_features(p2r_mlp* mlp, const p2r_opts* opts, int32_t n, const float* par, const float* q,
+                     const float* R, const float* s_label, float* x, float* t, float* s_line, void* stream);
+int p2r_mlp_forward(p2r_mlp* mlp, const float* x, float* y, int32_t B, void* stream);
+/* Gradients of the mean squared error over the batch (grads_out [n_params], loss_out [1]; nullable). */
+int p2r_mlp_grads(p2r_mlp* mlp, const float* x, const float* t, int32_t B, float* grads_out,
+                  float* loss_out, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights, then a fresh BF16 copy. */
+int p2r_mlp_train_step(p2r_mlp* mlp, const float* x, const float* t, int32_t B, float lr,
+                       float* loss_out, void* stream);
+/* Checkpoint (host file): step, FP32 weights and Adam moments; load restores them bit for bit. */
+int p2r_mlp_save(p2r_mlp* mlp, const char* path);
+int p2r_mlp_load(p2r_mlp* mlp, const char* path);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,8 @@
 //    the half-angle (sinc) form so it is exact at zero curvature;
 //  * crossing with a cylinder |xy| = R: intersection of the track circle
 //    with the layer circle (closed form); crossing with a plane z = Z:
-//    s = (Z - z) tan(theta);
+//    s = (Z - z) tan(theta); in both cases the next crossing along the
+//    motion, a surface at most 1 cm behind counting as the next one;
 //  * transport Jacobian J = d(state after)/d(state before), including the
 //    dependence of the path length on the start state, by dual numbers;
 //  * C' = J C J^T;
@@ -48,6 +49,10 @@ constexpr uint32_t ST_DONE = 1u << 31;
 
 // relative pivot threshold of the positive-definiteness test of S
 constexpr double PD_TAU = 1e-12;
+// how far behind the start point a surface may lie and still be the next
+// one (transverse path, cm): an update can leave the state slightly beyond
+// the next surface
+constexpr double BACK_TOL = 1.0;
 
 // ------------------------------------------------------------ dual numbers
 struct Dual {
@@ -117,7 +122,13 @@ void helix(const T p[6], double q, double bz, const T& s, T out[6]) {
 }
 
 // ------------------------------------------------- O2: crossing a cylinder
-// Smallest s > 0 with x(s)^2 + y(s)^2 = R^2.  Returns false if none.
+// The next crossing of x(s)^2 + y(s)^2 = R^2 along the direction of motion.
+// Candidates are the (at most two) crossings within half a turn of the
+// start, either way (heading change in (-pi, pi]); the crossing is the
+// candidate with the smallest s > -BACK_TOL.  Returns false if there is none
+// (in particular when the track circle and the layer circle do not meet).  For a state inside an outer layer and moving out
+// this is the first forward crossing; a state that the previous update left
+// slightly beyond the layer is taken back to it.
 template <class T>
 bool cross_cylinder(const T p[6], double q, double bz, double R, T* s_out) {
     const T& x = p[0]; const T& y = p[1]; const T& phi = p[4];
@@ -127,10 +138,10 @@ bool cross_cylinder(const T p[6], double q, double bz, double R, T* s_out) {
         T c = x * x + y * y - R * R;
         T disc = b * b - c;
         if (val(disc) < 0.0) return false;
-        T sp = -b + sqrt(disc);
         T sm = -b - sqrt(disc);
-        if (val(sm) > 0.0) { *s_out = sm; return true; }
-        if (val(sp) > 0.0) { *s_out = sp; return true; }
+        T sp = -b + sqrt(disc);
+        if (val(sm) > -BACK_TOL) { *s_out = sm; return true; }
+        if (val(sp) > -BACK_TOL) { *s_out = sp; return true; }
         return false;
     }
     // track circle: centre c, radius rho; P(s) - c = (sin phi', -cos phi')/omega
@@ -167,31 +178,37 @@ bool cross_cylinder(const T p[6], double q, double bz, double R, T* s_out) {
     for (int k = 0; k < 2; ++k) {
         T psi = k == 0 ? beta + gamma : beta - gamma;
         T dphi = psi + sgn * (0.5 * PI) - phi;     // heading change to the crossing
-        // s = dphi / omega must be positive: reduce dphi into sign(omega) * [0, 2 pi)
-        double turns = std::floor(sgn * val(dphi) / (2.0 * PI));
-        dphi = dphi - sgn * turns * (2.0 * PI);
+        // the crossing within half a turn: heading change in (-pi, pi]
+        double turns = std::floor((val(dphi) + PI) / (2.0 * PI));
+        dphi = dphi - turns * (2.0 * PI);
+        if (val(dphi) == -PI) dphi = dphi + 2.0 * PI;
         T s = dphi / w;
-        if (val(s) <= 1e-9) s = s + 2.0 * PI / fabs(w);   // the start point itself is not a crossing
+        if (!(val(s) > -BACK_TOL)) continue;
         if (!have || val(s) < val(best)) { best = s; have = true; }
     }
+    if (!have) return false;
     *s_out = best;
     return true;
 }
 
 // ---------------------------------------------------- O3: crossing a plane
 template <class T>
-bool cross_plane(const T p[6], double Z, T* s_out) {
+bool cross_plane(const T p[6], double q, double bz, double Z, T* s_out) {
+    // s = (Z - z) tan(theta); the plane must lie ahead (or at most BACK_TOL
+    // behind) and within half a turn, as for cylinders
     double ct = std::cos(val(p[5]));
     if (ct == 0.0) return false;
     T s = (Z - p[2]) * sin(p[5]) / cos(p[5]);
-    if (!(val(s) > 0.0)) return false;
+    if (!(val(s) > -BACK_TOL)) return false;
+    double w = -q * KAPPA * bz * val(p[3]);
+    if (std::fabs(w * val(s)) > PI) return false;
     *s_out = s;
     return true;
 }
 
 template <class T>
 bool path_to_surface(const T p[6], double q, double bz, int type, double v, T* s) {
-    return type == 0 ? cross_cylinder(p, q, bz, v, s) : cross_plane(p, v, s);
+    return type == 0 ? cross_cylinder(p, q, bz, v, s) : cross_plane(p, q, bz, v, s);
 }
 
 // Propagate p to the surface; fills the new state and (optionally) the 6x6
@@ -359,7 +376,9 @@ void fit_one(const FitArgs& a, int64_t t) {
     } else {
         for (int64_t h = a.offsets[t]; h < a.offsets[t + 1]; ++h) {
             const double* m = a.hits + h * 3;
-            if (!(std::isfinite(m[0]) && std::isfinite(m[1]) && std::isfinite(m[2]))) {
+            if (a.stype[h] > 1) {
+                st |= ST_BAD_INPUT;           // unknown surface type: surface skipped
+            } else if (!(std::isfinite(m[0]) && std::isfinite(m[1]) && std::isfinite(m[2]))) {
                 st |= ST_HIT_MISSING;
             } else {
                 double pp[6], J[36];

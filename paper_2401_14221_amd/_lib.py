@@ -32,7 +32,7 @@ class P2RError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("bz_tesla", C.c_float), ("newton_tol_cm", C.c_float), ("newton_max_iter", C.c_int32),
                 ("chi2_cut", C.c_float), ("fp64_fallback", C.c_int32), ("width", C.c_int32),
-                ("mlp", C.c_void_p)]
+                ("mlp", C.c_void_p), ("use_graph", C.c_int32), ("helix_evals", C.c_void_p)]
 
 
 _lib = None
@@ -64,8 +64,19 @@ def library():
         for f in (L.p2r_propagate_update, L.p2z_propagate_update):
             f.argtypes = [vp, C.POINTER(Opts), i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.p2r_autotune.argtypes = [vp, C.c_int, i32, i32, vp]
-        if hasattr(L, "fit_tracks_batched"):
-            L.fit_tracks_batched.argtypes = [vp, C.POINTER(Opts), i32] + [vp] * 13
+        L.fit_tracks_batched.argtypes = [vp, C.POINTER(Opts), i32, i64, i32] + [vp] * 13
+        L.p2r_mlp_create.argtypes = [vp, C.POINTER(vp)]
+        L.p2r_mlp_destroy.argtypes = [vp]
+        L.p2r_mlp_destroy.restype = None
+        L.p2r_mlp_n_params.restype = C.c_int
+        L.p2r_mlp_set_params.argtypes = [vp, vp]
+        L.p2r_mlp_get_params.argtypes = [vp, vp]
+        L.p2r_mlp_features.argtypes = [vp, C.POINTER(Opts), i32] + [vp] * 7 + [vp]
+        L.p2r_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
+        L.p2r_mlp_grads.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.p2r_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, vp, vp]
+        L.p2r_mlp_save.argtypes = [vp, C.c_char_p]
+        L.p2r_mlp_load.argtypes = [vp, C.c_char_p]
         _lib = L
     return _lib
 
@@ -158,7 +169,7 @@ class Context:
         return trk_out, chi2, status
 
     def fit_tracks_batched(self, offsets, surf_type, surf_val, hit_pos, hit_cov, par_in, cov_in, q,
-                           out=None, opts=None, stream=None, **kw):
+                           n_hits, max_surfaces, out=None, opts=None, stream=None, **kw):
         """Ragged CSR fit; returns (par_out, cov_out, chi2, status)."""
         opts = opts or default_opts(**kw)
         n = par_in.shape[0]
@@ -169,8 +180,81 @@ class Context:
                    torch.empty(n, dtype=torch.float32, device=dev),
                    torch.empty(n, dtype=torch.int32, device=dev))
         par_out, cov_out, chi2, status = out
-        _check(library().fit_tracks_batched(self._h, C.byref(opts), n, _ptr(offsets), _ptr(surf_type),
+        _check(library().fit_tracks_batched(self._h, C.byref(opts), n, int(n_hits), int(max_surfaces),
+                                            _ptr(offsets), _ptr(surf_type),
                                             _ptr(surf_val), _ptr(hit_pos), _ptr(hit_cov), _ptr(par_in),
                                             _ptr(cov_in), _ptr(q), _ptr(par_out), _ptr(cov_out), _ptr(chi2),
                                             _ptr(status), _stream(stream)))
         return par_out, cov_out, chi2, status
+
+
+class Mlp:
+    """Path-length MLP on the GPU (weights, Adam state and kernels in libp2r)."""
+
+    def __init__(self, ctx: Context, params=None):
+        self.ctx = ctx
+        self._h = vp()
+        _check(library().p2r_mlp_create(ctx._h, C.byref(self._h)))
+        self.n_params = library().p2r_mlp_n_params()
+        if params is not None:
+            self.set_params(params)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            library().p2r_mlp_destroy(self._h)
+            self._h = vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(library().p2r_mlp_set_params(self._h, a.ctypes.data_as(C.c_void_p)))
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(library().p2r_mlp_get_params(self._h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def features(self, par, q, R, s_label=None, stream=None, **kw):
+        """Device tensors par (n,6), q (n,), R (n,) [, s_label (n,)] -> x (n,7), t (n,) or None, s_line (n,)."""
+        n = par.shape[0]
+        dev = par.device
+        x = torch.empty((n, 7), dtype=torch.float32, device=dev)
+        sl = torch.empty(n, dtype=torch.float32, device=dev)
+        t = torch.empty(n, dtype=torch.float32, device=dev) if s_label is not None else None
+        o = default_opts(**kw)
+        _check(library().p2r_mlp_features(self._h, C.byref(o), n, _ptr(par), _ptr(q), _ptr(R), _ptr(s_label),
+                                          _ptr(x), _ptr(t), _ptr(sl), _stream(stream)))
+        return x, t, sl
+
+    def forward(self, x, stream=None):
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(library().p2r_mlp_forward(self._h, _ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+        return y
+
+    def grads(self, x, t, stream=None):
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(library().p2r_mlp_grads(self._h, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss), _stream(stream)))
+        return g, loss
+
+    def train_step(self, x, t, lr, loss_out=None, stream=None):
+        _check(library().p2r_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], float(lr), _ptr(loss_out),
+                                            _stream(stream)))
+
+    def save(self, path):
+        _check(library().p2r_mlp_save(self._h, path.encode()))
+
+    def load(self, path):
+        _check(library().p2r_mlp_load(self._h, path.encode()))

@@ -17,7 +17,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
-SOURCES = ["kernels.hip", "capi.cpp"]
+SOURCES = ["kernels.hip", "ragged.hip", "mlp.hip", "capi.cpp"]
 
 
 def build(verbose: bool = False) -> str:

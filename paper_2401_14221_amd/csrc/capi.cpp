@@ -2,6 +2,7 @@
 // the ragged-fit graph.  Declarations and semantics are in include/p2r.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -15,6 +16,7 @@
 
 #include "../../include/p2r.h"
 #include "launch.h"
+#include "mlp.h"
 #include "track_math.h"
 
 namespace {
@@ -52,12 +54,17 @@ struct DeviceGuard {
 
 }  // namespace
 
-struct RaggedShape {
-    int32_t n = -1;
-    int64_t H = -1;
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
+// Arguments a captured ragged graph was recorded with; a call with other
+// arguments re-captures.
+struct RaggedKey {
+    p2r::RaggedLaunch a{};
+    p2r::Params P{};
+    const void* fn = nullptr;
     hipStream_t stream = nullptr;
+    bool same(const RaggedKey& o) const {
+        return std::memcmp(&a, &o.a, sizeof a) == 0 && std::memcmp(&P, &o.P, sizeof P) == 0 && fn == o.fn &&
+               stream == o.stream;
+    }
 };
 
 struct p2r_ctx {
@@ -69,10 +76,22 @@ struct p2r_ctx {
     int chosen[3] = {-1, -1, -1};    // variant index per `which`
     std::map<std::string, std::string> cache;  // key -> variant name
     // ragged workspace (owned)
-    p2r::RaggedLaunch rag{};
-    size_t rag_n_cap = 0, rag_nb_cap = 0;
-    int rag_lmax = 0;
-    RaggedShape shape;
+    int32_t* rag_hist = nullptr;
+    int32_t* rag_work = nullptr;
+    int32_t* rag_perm = nullptr;
+    int32_t* rag_keys = nullptr;
+    int32_t rag_n_cap = 0, rag_nkeys_cap = 0;
+    int rag_blocks_per_cu[2] = {0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    RaggedKey key;
+    bool have_graph = false;
+};
+
+struct p2r_mlp {
+    int device = 0;
+    p2r::MlpDev d{};
+    void* block = nullptr;   // one allocation holding every buffer
 };
 
 namespace {
@@ -86,21 +105,28 @@ const p2r::Variant* find_variant(int which, const std::string& name) {
 int default_variant(int which) {
     const auto& vs = p2r::variants();
     for (size_t i = 0; i < vs.size(); ++i)
-        if (vs[i].which == which) return (int)i;
+        if (vs[i].which == which && !vs[i].learned) return (int)i;
     return -1;
 }
 
-int variant_for(p2r_ctx* ctx, int which, int width, const p2r::Variant** out) {
+int variant_for(p2r_ctx* ctx, int which, int width, const p2r::Variant** out, bool learned = false) {
     const auto& vs = p2r::variants();
     int idx = ctx->chosen[which] >= 0 ? ctx->chosen[which] : default_variant(which);
     if (idx < 0) return fail(P2R_ENOTUNED, "no kernel variant compiled for which=%d", which);
+    if (learned) {
+        const int w = width != 0 ? width : vs[idx].width;
+        for (const auto& v : vs)
+            if (v.which == which && v.learned && v.width == w) { *out = &v; return P2R_OK; }
+        return fail(P2R_ELAYOUT, "no learned-start kernel for width %d", w);
+    }
     if (width != 0 && vs[idx].width != width) {
         // first variant of this width (prefer the tuned occupancy/unroll when it matches)
         idx = -1;
         for (size_t i = 0; i < vs.size(); ++i)
-            if (vs[i].which == which && vs[i].width == width) { idx = (int)i; break; }
+            if (vs[i].which == which && vs[i].width == width && !vs[i].learned) { idx = (int)i; break; }
         if (idx < 0) return fail(P2R_ELAYOUT, "layout width %d not supported (32, 64, 128, 256 for p2r; 64 for p2z)", width);
     }
+    (void)0;
     *out = &vs[idx];
     return P2R_OK;
 }
@@ -121,7 +147,7 @@ int check_opts(const p2r_opts* o) {
     if (!(o->newton_tol_cm > 0.0f) || !std::isfinite(o->newton_tol_cm)) return fail(P2R_EINVAL, "newton_tol_cm must be > 0");
     if (o->newton_max_iter < 1 || o->newton_max_iter > 64) return fail(P2R_EINVAL, "newton_max_iter must be in [1, 64]");
     if (std::isnan(o->chi2_cut)) return fail(P2R_EINVAL, "chi2_cut is NaN");
-    if (o->fp64_fallback < 0 || o->fp64_fallback > 2) return fail(P2R_EINVAL, "fp64_fallback must be 0, 1 or 2");
+    if (o->fp64_fallback < 0 || o->fp64_fallback > 3) return fail(P2R_EINVAL, "fp64_fallback must be 0, 1, 2 or 3");
     return P2R_OK;
 }
 
@@ -179,9 +205,11 @@ void p2r_opts_default(p2r_opts* o) {
     o->newton_tol_cm = 1e-6f;
     o->newton_max_iter = 8;
     o->chi2_cut = 0.0f;
-    o->fp64_fallback = 1;
+    o->fp64_fallback = 3;
     o->width = 0;
     o->mlp = nullptr;
+    o->use_graph = 1;
+    o->helix_evals = nullptr;
 }
 
 int p2r_ctx_create(p2r_ctx** out, int device, const char* tune_cache_path) {
@@ -209,10 +237,9 @@ int p2r_ctx_create(p2r_ctx** out, int device, const char* tune_cache_path) {
 void p2r_ctx_destroy(p2r_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard g(ctx->device);
-    if (ctx->shape.exec) (void)hipGraphExecDestroy(ctx->shape.exec);
-    if (ctx->shape.graph) (void)hipGraphDestroy(ctx->shape.graph);
-    void* bufs[] = {ctx->rag.counts, ctx->rag.perm, ctx->rag.work, ctx->rag.trk_pack, ctx->rag.hit_pack,
-                    ctx->rag.blk_len};
+    if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    void* bufs[] = {ctx->rag_hist, ctx->rag_work, ctx->rag_perm, ctx->rag_keys};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete ctx;
@@ -254,11 +281,14 @@ static int propagate_common(int which, p2r_ctx* ctx, const p2r_opts* opts, int32
         if (p && !aligned(p, 4)) return fail(P2R_ELAYOUT, "buffer not 4-byte aligned");
     if ((const void*)trk_in == (const void*)trk_out) return fail(P2R_EINVAL, "trk_in and trk_out must not alias");
     const p2r::Variant* v = nullptr;
-    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v);
+    const p2r_mlp* mlp = static_cast<const p2r_mlp*>(opts->mlp);
+    if (mlp && mlp->device != ctx->device) return fail(P2R_EINVAL, "mlp lives on device %d, context on %d", mlp->device, ctx->device);
+    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v, mlp != nullptr);
     if (rc) return rc;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-    p2r::FitLaunch a{n_tracks, n_layers, surf, trk_in, hits, trk_out, chi2_out, status, opts->mlp};
+    p2r::FitLaunch a{n_tracks, n_layers, surf, trk_in, hits, trk_out, chi2_out, status,
+                     mlp ? (const void*)mlp->d.w : nullptr, opts->helix_evals};
     hipError_t e = p2r::launch_fit(*v, a, params_of(opts), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return P2R_OK;
@@ -277,6 +307,280 @@ int p2z_propagate_update(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, i
     return propagate_common(1, ctx, opts, n_tracks, n_layers, layer_z, trk_in, hits, trk_out, chi2_out, status,
                             stream);
 }
+
+int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits, int32_t max_surfaces,
+                       const int64_t* offsets, const uint8_t* surf_type, const float* surf_val,
+                       const float* hit_pos, const float* hit_cov, const float* par_in, const float* cov_in,
+                       const int8_t* q, float* par_out, float* cov_out, float* chi2_out, uint32_t* status,
+                       void* stream) {
+    if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (opts->mlp) return fail(P2R_EINVAL, "the learned start is not available in the ragged fit");
+    if (n_tracks < 0 || n_hits < 0) return fail(P2R_EINVAL, "negative size (n_tracks %d, n_hits %lld)", n_tracks,
+                                                (long long)n_hits);
+    if (max_surfaces < 0 || max_surfaces > 255) return fail(P2R_EINVAL, "max_surfaces must be in [0, 255]");
+    if (n_hits > (int64_t)n_tracks * max_surfaces)
+        return fail(P2R_EINVAL, "n_hits %lld exceeds n_tracks * max_surfaces", (long long)n_hits);
+    if (n_tracks == 0) return P2R_OK;
+    if (!offsets || !par_in || !cov_in || !q || !par_out || !cov_out || !chi2_out || !status ||
+        (n_hits > 0 && (!surf_type || !surf_val || !hit_pos || !hit_cov)))
+        return fail(P2R_EINVAL, "NULL buffer");
+    const void* a8[] = {offsets};
+    const void* a4[] = {surf_val, hit_pos, hit_cov, par_in, cov_in, par_out, cov_out, chi2_out, status};
+    for (const void* p : a8)
+        if (!aligned(p, 8)) return fail(P2R_ELAYOUT, "offsets not 8-byte aligned");
+    for (const void* p : a4)
+        if (p && !aligned(p, 4)) return fail(P2R_ELAYOUT, "buffer not 4-byte aligned");
+    const p2r::Variant* v = nullptr;
+    rc = variant_for(ctx, 2, 0, &v);
+    if (rc) return rc;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e;
+    // workspace
+    const int nkeys = p2r::ragged_nkeys(max_surfaces);
+    if (n_tracks > ctx->rag_n_cap) {
+        if (ctx->rag_perm) (void)hipFree(ctx->rag_perm);
+        if (ctx->rag_keys) (void)hipFree(ctx->rag_keys);
+        ctx->rag_perm = ctx->rag_keys = nullptr;
+        ctx->rag_n_cap = 0;
+        if ((e = hipMalloc(&ctx->rag_perm, sizeof(int32_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&ctx->rag_keys, sizeof(int32_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        ctx->rag_n_cap = n_tracks;
+    }
+    if (nkeys > ctx->rag_nkeys_cap) {
+        if (ctx->rag_hist) (void)hipFree(ctx->rag_hist);
+        ctx->rag_hist = nullptr;
+        ctx->rag_nkeys_cap = 0;
+        if ((e = hipMalloc(&ctx->rag_hist, sizeof(int32_t) * nkeys)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        ctx->rag_nkeys_cap = nkeys;
+    }
+    if (!ctx->rag_work && (e = hipMalloc(&ctx->rag_work, sizeof(int32_t))) != hipSuccess)
+        return hip_fail(e, "hipMalloc");
+    const int slot = v->waves_per_eu == 4 ? 1 : 0;
+    if (ctx->rag_blocks_per_cu[slot] == 0) {
+        int nb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, p2r::RAG_W, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        ctx->rag_blocks_per_cu[slot] = nb > 0 ? nb : 1;
+    }
+    p2r::RaggedLaunch a{};
+    a.n = n_tracks;
+    a.lmax = max_surfaces;
+    a.n_hits = n_hits;
+    a.offsets = offsets;
+    a.stype = surf_type;
+    a.sval = surf_val;
+    a.hpos = hit_pos;
+    a.hcov = hit_cov;
+    a.par_in = par_in;
+    a.cov_in = cov_in;
+    a.q = q;
+    a.par_out = par_out;
+    a.cov_out = cov_out;
+    a.chi2 = chi2_out;
+    a.status = status;
+    a.hist = ctx->rag_hist;
+    a.work = ctx->rag_work;
+    a.perm = ctx->rag_perm;
+    a.keys = ctx->rag_keys;
+    a.nkeys = nkeys;
+    a.nb = (n_tracks + p2r::RAG_W - 1) / p2r::RAG_W;
+    a.grid = std::min(a.nb, ctx->cu_count * ctx->rag_blocks_per_cu[slot]);
+    p2r::Params P = params_of(opts);
+    hipStream_t s = (hipStream_t)stream;
+    if (!opts->use_graph || s == nullptr) {
+        e = p2r::launch_ragged(*v, a, P, s);
+        if (e != hipSuccess) return hip_fail(e, "ragged launch");
+        return P2R_OK;
+    }
+    RaggedKey k;
+    k.a = a;
+    k.P = P;
+    k.fn = v->fn;
+    k.stream = s;
+    if (!ctx->have_graph || !ctx->key.same(k)) {
+        if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        ctx->exec = nullptr;
+        ctx->graph = nullptr;
+        ctx->have_graph = false;
+        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t el = p2r::launch_ragged(*v, a, P, s);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(s, &graph);
+        if (el != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(el, "ragged launch during capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        ctx->graph = graph;
+        ctx->exec = exec;
+        ctx->key = k;
+        ctx->have_graph = true;
+    }
+    if ((e = hipGraphLaunch(ctx->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return P2R_OK;
+}
+
+// ------------------------------------------------------------------- MLP
+
+static int mlp_check(p2r_mlp* m) { return m ? P2R_OK : fail(P2R_EINVAL, "mlp is NULL"); }
+
+int p2r_mlp_create(p2r_ctx* ctx, p2r_mlp** out) {
+    if (!ctx || !out) return fail(P2R_EINVAL, "NULL argument");
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    std::unique_ptr<p2r_mlp> m(new p2r_mlp());
+    m->device = ctx->device;
+    const size_t np = p2r::MLP_NPARAM;
+    const size_t fl = (4 * np + 64) * sizeof(float);
+    const size_t bytes = fl + sizeof(p2r::MlpWeights) + 256;
+    hipError_t e = hipMalloc(&m->block, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMemset(m->block, 0, bytes)) != hipSuccess) { (void)hipFree(m->block); return hip_fail(e, "hipMemset"); }
+    float* f = static_cast<float*>(m->block);
+    m->d.master = f;
+    m->d.m = f + np;
+    m->d.v = f + 2 * np;
+    m->d.grad = f + 3 * np;
+    m->d.loss = f + 4 * np;
+    uintptr_t wp = (reinterpret_cast<uintptr_t>(f + 4 * np + 64) + 255) & ~uintptr_t(255);
+    m->d.w = reinterpret_cast<p2r::MlpWeights*>(wp);
+    m->d.step = 0;
+    *out = m.release();
+    return P2R_OK;
+}
+
+void p2r_mlp_destroy(p2r_mlp* m) {
+    if (!m) return;
+    DeviceGuard g(m->device);
+    if (m->block) (void)hipFree(m->block);
+    delete m;
+}
+
+int p2r_mlp_set_params(p2r_mlp* m, const float* host_params) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!host_params) return fail(P2R_EINVAL, "host_params is NULL");
+    DeviceGuard g(m->device);
+    const size_t nb = p2r::MLP_NPARAM * sizeof(float);
+    hipError_t e = hipMemcpy(m->d.master, host_params, nb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(m->d.m, 0, 2 * nb);
+    if (e == hipSuccess) e = p2r::mlp_recast(m->d, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "p2r_mlp_set_params");
+    m->d.step = 0;
+    return P2R_OK;
+}
+
+int p2r_mlp_get_params(p2r_mlp* m, float* host_params) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!host_params) return fail(P2R_EINVAL, "host_params is NULL");
+    DeviceGuard g(m->device);
+    hipError_t e = hipMemcpy(host_params, m->d.master, p2r::MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost);
+    return e == hipSuccess ? P2R_OK : hip_fail(e, "p2r_mlp_get_params");
+}
+
+int p2r_mlp_n_params(void) { return p2r::MLP_NPARAM; }
+
+int p2r_mlp_features(p2r_mlp* m, const p2r_opts* opts, int32_t n, const float* par, const float* q, const float* R,
+                     const float* s_label, float* x, float* t, float* s_line, void* stream) {
+    int rc = mlp_check(m);
+    if (!rc) rc = check_opts(opts);
+    if (rc) return rc;
+    if (n < 0) return fail(P2R_EINVAL, "negative n");
+    if (n == 0) return P2R_OK;
+    if (!par || !q || !R || !x || (t && !s_label)) return fail(P2R_EINVAL, "NULL buffer");
+    DeviceGuard g(m->device);
+    hipError_t e = p2r::mlp_features(n, par, q, R, s_label, opts->bz_tesla, x, t, s_line, (hipStream_t)stream);
+    return e == hipSuccess ? P2R_OK : hip_fail(e, "mlp features");
+}
+
+int p2r_mlp_forward(p2r_mlp* m, const float* x, float* y, int32_t B, void* stream) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (B < 0) return fail(P2R_EINVAL, "negative batch");
+    if (B > 0 && (!x || !y)) return fail(P2R_EINVAL, "NULL buffer");
+    DeviceGuard g(m->device);
+    hipError_t e = p2r::mlp_forward(m->d, x, y, B, (hipStream_t)stream);
+    return e == hipSuccess ? P2R_OK : hip_fail(e, "mlp forward");
+}
+
+int p2r_mlp_grads(p2r_mlp* m, const float* x, const float* t, int32_t B, float* grads_out, float* loss_out,
+                  void* stream) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (B <= 0) return fail(P2R_EINVAL, "batch must be positive");
+    if (!x || !t) return fail(P2R_EINVAL, "NULL buffer");
+    DeviceGuard g(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = p2r::mlp_grads(m->d, x, t, B, s);
+    if (e == hipSuccess && grads_out)
+        e = hipMemcpyAsync(grads_out, m->d.grad, p2r::MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && loss_out) e = hipMemcpyAsync(loss_out, m->d.loss, sizeof(float), hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? P2R_OK : hip_fail(e, "mlp grads");
+}
+
+int p2r_mlp_train_step(p2r_mlp* m, const float* x, const float* t, int32_t B, float lr, float* loss_out,
+                       void* stream) {
+    int rc = p2r_mlp_grads(m, x, t, B, nullptr, loss_out, stream);
+    if (rc) return rc;
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(P2R_EINVAL, "lr must be > 0");
+    DeviceGuard g(m->device);
+    m->d.step += 1;
+    hipError_t e = p2r::mlp_adam(m->d, lr, m->d.step, (hipStream_t)stream);
+    return e == hipSuccess ? P2R_OK : hip_fail(e, "mlp adam");
+}
+
+// checkpoint: magic, step, then master weights, Adam m and v (FP32)
+int p2r_mlp_save(p2r_mlp* m, const char* path) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!path) return fail(P2R_EINVAL, "path is NULL");
+    DeviceGuard g(m->device);
+    std::vector<float> buf(3 * (size_t)p2r::MLP_NPARAM);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(buf.data(), m->d.master, buf.size() * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "p2r_mlp_save");
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(P2R_EINVAL, "cannot open %s", path);
+    const uint32_t hdr[4] = {0x504D4C50u /* "PLMP" */, 1u, (uint32_t)p2r::MLP_NPARAM, (uint32_t)m->d.step};
+    bool ok = std::fwrite(hdr, sizeof hdr, 1, f) == 1 && std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? P2R_OK : fail(P2R_EINVAL, "write to %s failed", path);
+}
+
+int p2r_mlp_load(p2r_mlp* m, const char* path) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (!path) return fail(P2R_EINVAL, "path is NULL");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(P2R_EINVAL, "cannot open %s", path);
+    uint32_t hdr[4];
+    std::vector<float> buf(3 * (size_t)p2r::MLP_NPARAM);
+    bool ok = std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == 0x504D4C50u && hdr[1] == 1u &&
+              hdr[2] == (uint32_t)p2r::MLP_NPARAM && std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return fail(P2R_EINVAL, "%s is not a p2r MLP checkpoint", path);
+    DeviceGuard g(m->device);
+    hipError_t e = hipMemcpy(m->d.master, buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = p2r::mlp_recast(m->d, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "p2r_mlp_load");
+    m->d.step = (int32_t)hdr[3];
+    return P2R_OK;
+}
+
 
 int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, void* stream) {
     if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
@@ -327,12 +631,12 @@ int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, vo
     int best_i = -1;
     int cur_w = -1;
     for (size_t i = 0; i < vs.size(); ++i) {
-        if (vs[i].which != which) continue;
+        if (vs[i].which != which || vs[i].learned) continue;
         if (vs[i].width != cur_w) {
             TRY(p2r::launch_synth(which, vs[i].width, n_tracks, n_layers, surf, trk, hits, s), "synthetic fill");
             cur_w = vs[i].width;
         }
-        p2r::FitLaunch a{n_tracks, n_layers, surf, trk, hits, out, chi2, st, nullptr};
+        p2r::FitLaunch a{n_tracks, n_layers, surf, trk, hits, out, chi2, st, nullptr, nullptr};
         for (int w = 0; w < 2; ++w) TRY(p2r::launch_fit(vs[i], a, P, s), "kernel launch");
         TRY(hipEventRecord(e0, s), "hipEventRecord");
         const int reps = 5;

@@ -4,6 +4,7 @@
 // layer's hit prefetched while the current layer is computed; results are
 // written once at the end.
 #include "launch.h"
+#include "mlp_dev.h"
 #include "track_math.h"
 
 namespace p2r {
@@ -24,21 +25,40 @@ __device__ __forceinline__ void store_track(float* __restrict__ t, int W, const 
     t[27 * W] = st.q;
 }
 
-// p2r: hits [block][layer][9][W]
-template <int W, int UNROLL>
-__device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P) {
+__device__ __forceinline__ void count_evals(unsigned long long* evals, int iters) {
+    if (!evals) return;
+    unsigned long long v = (unsigned long long)iters;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (__lane_id() == 0) atomicAdd(evals, v);
+}
+
+// p2r: hits [block][layer][9][W].  LEARNED: the path-length MLP proposes the
+// start of every helix-to-cylinder solve; the whole wave evaluates it on the
+// matrix cores, so every lane stays in the layer loop (lanes past n shadow
+// the last track and write nothing).
+template <int W, int UNROLL, bool LEARNED>
+__device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, MlpWeights* Wl) {
+    if (LEARNED) {
+        const uint32_t* s = reinterpret_cast<const uint32_t*>(a.mlp);
+        uint32_t* d = reinterpret_cast<uint32_t*>(Wl);
+        for (int i = threadIdx.x; i < (int)(sizeof(MlpWeights) / 4); i += blockDim.x) d[i] = s[i];
+        __syncthreads();
+    }
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= a.n) return;
-    const int b = gid / W, l = gid % W;
+    const bool active = gid < a.n;
+    if (!LEARNED && !active) return;
+    const int g = active ? gid : a.n - 1;
+    const int b = g / W, l = g % W;
     const float* tin = a.trk_in + (size_t)b * (28 * W) + l;
     State st;
     load_track(tin, W, st);
     uint32_t flags = 0;
-    int nused = 0;
+    int nused = 0, evals = 0;
     float chi2 = 0.0f;
-    if (bad_input(st)) {
-        flags = ST_BAD_INPUT;
-    } else {
+    const bool bad = bad_input(st);
+    if (bad) flags = ST_BAD_INPUT;
+    if (!bad || LEARNED) {
         const float* hb = a.hits + (size_t)b * ((size_t)a.L * 9 * W) + l;
         float hm[9];
 #pragma unroll
@@ -53,12 +73,27 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P) {
                 for (int k = 0; k < 9; ++k) hm[k] = hn[k * W];
             }
             const float R = a.surf[ly];
-            float c2 = 0.0f;
-            StepOut o = step_cylinder(st, R, m, V, P, c2, newton_tol(P.tol, R), -1.0f);
-            flags |= o.flags;
-            if (o.updated) { ++nused; chi2 += c2; }
+            float s_start = NAN;
+            if (LEARNED) {
+                float sphi, cphi;
+                sincosf(st.p[4], &sphi, &cphi);
+                const float w = -st.q * KAPPA * P.bz * st.p[3];
+                float feat[MLP_IN], sl;
+                const bool ok = mlp_features_of(st.p[0], st.p[1], cphi, sphi, w, R, feat, sl);
+                const float yv = mlp_infer(*Wl, feat);            // whole wave
+                if (ok && !bad && finite3(m)) s_start = sl * (1.0f + yv * (1.0f / MLP_TARGET_SCALE));
+            }
+            if (!bad) {
+                float c2 = 0.0f;
+                StepOut o = step_cylinder(st, R, m, V, P, c2, newton_tol(P.tol, R), s_start, MLP_ACCEPT_CM);
+                flags |= o.flags;
+                evals += o.iters;
+                if (o.updated) { ++nused; chi2 += c2; }
+            }
         }
     }
+    count_evals(a.evals, active ? evals : 0);
+    if (!active) return;
     store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
     a.chi2[gid] = chi2;
     a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
@@ -110,7 +145,15 @@ __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
 #define P2R_KERNEL(W, WPE, U)                                                              \
     __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256),                \
                                    amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))               \
-    p2r_w##W##_e##WPE##_u##U(FitLaunch a, Params P) { p2r_body<W, U>(a, P); }
+    p2r_w##W##_e##WPE##_u##U(FitLaunch a, Params P) { p2r_body<W, U, false>(a, P, nullptr); }
+
+#define P2R_LEARNED_KERNEL(W, WPE, U)                                                      \
+    __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256),                \
+                                   amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))               \
+    p2r_mlp_w##W##_e##WPE##_u##U(FitLaunch a, Params P) {                                 \
+        __shared__ MlpWeights Wl;                                                          \
+        p2r_body<W, U, true>(a, P, &Wl);                                                   \
+    }
 
 #define P2Z_KERNEL(WPE, U)                                                                 \
     __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256),                \
@@ -126,12 +169,19 @@ P2R_KERNEL(64, 5, 1)
 P2R_KERNEL(64, 0, 2)
 P2R_KERNEL(128, 4, 1)
 P2R_KERNEL(256, 4, 1)
+P2R_LEARNED_KERNEL(64, 0, 1)
+P2R_LEARNED_KERNEL(128, 0, 1)
+P2R_LEARNED_KERNEL(256, 0, 1)
+P2R_LEARNED_KERNEL(32, 0, 1)
 P2Z_KERNEL(0, 1)
 P2Z_KERNEL(4, 1)
 P2Z_KERNEL(5, 1)
 P2Z_KERNEL(0, 2)
 
-#define VAR(WH, W, E, U, K) Variant{WH, W, E, U, #K, (const void*)&K}
+#define VAR(WH, W, E, U, K) Variant{WH, W, E, U, #K, (const void*)&K, false}
+#define VARL(W, E, U, K) Variant{0, W, E, U, #K, (const void*)&K, true}
+
+const void* ragged_fit_symbol(int wpe);   // ragged.hip
 
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = {
@@ -148,6 +198,12 @@ const std::vector<Variant>& variants() {
         VAR(1, 64, 4, 1, p2z_w64_e4_u1),
         VAR(1, 64, 5, 1, p2z_w64_e5_u1),
         VAR(1, 64, 0, 2, p2z_w64_e0_u2),
+        Variant{2, RAG_W, 0, 1, "rag_fit_e0", ragged_fit_symbol(0), false},   // default ragged
+        Variant{2, RAG_W, 4, 1, "rag_fit_e4", ragged_fit_symbol(4), false},
+        VARL(64, 0, 1, p2r_mlp_w64_e0_u1),     // learned start, one per width
+        VARL(128, 0, 1, p2r_mlp_w128_e0_u1),
+        VARL(256, 0, 1, p2r_mlp_w256_e0_u1),
+        VARL(32, 0, 1, p2r_mlp_w32_e0_u1),
     };
     return v;
 }
@@ -213,11 +269,11 @@ __global__ void synth_kernel(int which, int W, int32_t n, int32_t L, float* surf
             HelixPt h;
             float s = 0.0f;
             int it = 0;
-            bool ok;
+            bool ok, lok;
             if (which == 0) {
                 ok = cylinder_reachable(x, y, cphi, sphi, w, S) &&
                      newton_cylinder(x, y, cphi, sphi, w, S, newton_tol(1e-6f, S), 16,
-                                     line_path(x, y, cphi, sphi, S), s, h, it);
+                                     line_path(x, y, cphi, sphi, S, &lok), s, h, it);
             } else {
                 float Z = eta > 0 ? S : -S;
                 s = (Z - z) / cot;

@@ -18,6 +18,7 @@ struct Variant {
     int unroll;       // layer-loop unroll
     const char* name;
     const void* fn;   // kernel symbol
+    bool learned;     // p2r with the MLP start
 };
 
 const std::vector<Variant>& variants();
@@ -31,14 +32,20 @@ struct FitLaunch {
     float* chi2;
     uint32_t* status;
     const void* mlp;          // device MLP weights block (learned start) or null
+    unsigned long long* evals;  // nullable: total helix evaluations (diagnostics)
 };
 
 hipError_t launch_fit(const Variant& v, const FitLaunch& a, const Params& P, hipStream_t s);
 
-// Ragged path
+// Ragged path: tracks sorted by (surface count descending, |cot theta| bin),
+// then one persistent kernel over blocks of 64 sorted tracks.
+constexpr int RAG_W = 64;
+constexpr int RAG_ETA_BINS = 8;
+
 struct RaggedLaunch {
     int32_t n;                 // tracks
-    int64_t H;                 // total surfaces
+    int32_t lmax;              // largest surface count a track may have
+    int64_t n_hits;            // surfaces in total (bound of every CSR range)
     const int64_t* offsets;
     const uint8_t* stype;
     const float* sval;
@@ -51,19 +58,17 @@ struct RaggedLaunch {
     float* cov_out;
     float* chi2;
     uint32_t* status;
-    // workspace (device)
-    int32_t* counts;           // [lmax+2] histogram / offsets of surface counts
-    int32_t* perm;             // [n] packed order -> track index
+    // workspace (device, owned by the context)
+    int32_t* hist;             // [nkeys] key histogram, then bucket cursors
     int32_t* work;             // [1] work-queue counter
-    float* trk_pack;           // [nb][28][W]
-    float* hit_pack;           // [nb][lmax][11][W]  (9 hit values + surface value + type)
-    int32_t* blk_len;          // [nb] surfaces of the longest track of each block
-    int32_t nb;
-    int32_t lmax;
-    int32_t grid;              // persistent grid size
+    int32_t* perm;             // [n] sorted position -> track index
+    int32_t* keys;             // [n] sort key of every track
+    int32_t nkeys;
+    int32_t nb;                // blocks of RAG_W sorted tracks
+    int32_t grid;              // persistent grid (one wave per workgroup)
 };
 
+int ragged_nkeys(int lmax);
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s);
-int ragged_lmax_limit();
 
 }  // namespace p2r

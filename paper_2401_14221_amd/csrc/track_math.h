@@ -116,40 +116,96 @@ __device__ __forceinline__ bool cylinder_reachable(float x, float y, float cphi,
     return t <= 2.0f * (R - sg * ap) && -t <= 2.0f * (R + sg * ap);
 }
 
-// Straight-line path to |xy| = R (first positive root), or -1 if none.
-__device__ __forceinline__ float line_path(float x, float y, float cphi, float sphi, float R) {
+// How far behind the start a surface may lie and still be the next one
+// (transverse path, cm): an update can leave the state slightly beyond the
+// next surface, which a short backward step then reaches.
+constexpr float BACK_TOL = 1.0f;
+
+// Straight-line path to |xy| = R: the first root beyond -BACK_TOL.  With
+// b = x cos(phi) + y sin(phi) and d = R^2 - r0^2 the roots are
+// -b -/+ sqrt(b^2 + d), each taken in its cancellation-free form.  *ok is
+// false when no root lies beyond -BACK_TOL.
+__device__ __forceinline__ float line_path(float x, float y, float cphi, float sphi, float R, bool* ok) {
     float b = x * cphi + y * sphi;
     float r0sq = fmaf(x, x, y * y);
     float dr2 = R * R - r0sq;
     float disc = fmaf(b, b, dr2);
-    if (disc < 0.0f) return -1.0f;
-    float sq = sqrtf(disc);
-    if (dr2 >= 0.0f) {  // outward: one positive root, cancellation-free form
-        float den = b + sq;
-        return den > 0.0f ? dr2 / den : -1.0f;
+    float sq = sqrtf(fmaxf(disc, 0.0f));
+    float lo, hi;   // lo <= hi
+    if (b >= 0.0f) {
+        lo = -(b + sq);
+        hi = (b + sq) > 0.0f ? dr2 / (b + sq) : 0.0f;
+    } else {
+        lo = dr2 / (b - sq);
+        hi = sq - b;
     }
-    // inward: both roots positive when moving in (b < 0); the nearer one
-    return b < 0.0f ? dr2 / (b - sq) : -1.0f;
+    *ok = disc >= 0.0f && hi > -BACK_TOL;
+    return lo > -BACK_TOL ? lo : hi;
+}
+
+// Closed-form crossing of |xy| = R within half a turn, in FP32 without
+// cancellation.  With b = x cos(phi) + y sin(phi), a = y cos(phi) - x sin(phi),
+// d = R^2 - r0^2 and t = tan(omega s / 2), the crossing condition
+// |P(s)|^2 = R^2 is the quadratic alpha c^2 + 2 b c - d = 0 in c = 2 t / omega,
+// alpha = 1 + a omega - omega^2 d / 4, with roots c = d / (b +- sqrt(b^2 + alpha d));
+// then s = c atan(t) / t.  Each root is a crossing with turning angle in
+// (-pi, pi); the one returned is the smallest s > -BACK_TOL.  Returns false
+// if none (b^2 + alpha d < 0: the circles do not meet).
+__device__ __forceinline__ float atan_ratio(float t) {   // atan(t) / t
+    float at = fabsf(t);
+    if (at < 0.25f) {
+        float t2 = t * t;
+        return 1.0f + t2 * (-1.0f / 3.0f + t2 * (1.0f / 5.0f + t2 * (-1.0f / 7.0f + t2 * (1.0f / 9.0f))));
+    }
+    return atanf(t) / t;
+}
+
+__device__ __forceinline__ bool closed_form_cylinder(float x, float y, float cphi, float sphi, float w, float R,
+                                                     float& s_out) {
+    float b = x * cphi + y * sphi;
+    float a = y * cphi - x * sphi;
+    float d = R * R - fmaf(x, x, y * y);
+    float alpha = 1.0f + a * w - 0.25f * w * w * d;
+    float disc = fmaf(b, b, alpha * d);
+    if (disc < 0.0f) return false;
+    float sq = sqrtf(disc);
+    float den[2] = {b + sq, b - sq};
+    bool have = false;
+    float best = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        float s;
+        if (den[k] == 0.0f) {
+            if (w == 0.0f) continue;             // line root at infinity
+            s = PI_F / fabsf(w);                 // t = +-inf: exactly half a turn
+        } else {
+            float c = d / den[k];
+            float t = 0.5f * w * c;
+            s = c * atan_ratio(t);
+        }
+        if (s > -BACK_TOL && (!have || s < best)) { best = s; have = true; }
+    }
+    s_out = best;
+    return have;
 }
 
 // Newton iteration on f(s) = (r(s)^2 - R^2) / (2R) (= r - R near the root)
-// from s0.  Stops when |f| <= tol; returns false after max_iter helix
-// evaluations without convergence.  h holds the last evaluation.
+// from s0 (the straight-line root or a proposal).  Stops when |f| <= tol; returns false
+// after max_iter helix evaluations without convergence.  h holds the last
+// evaluation.
 __device__ __forceinline__ bool newton_cylinder(float x, float y, float cphi, float sphi, float w, float R,
                                                 float tol, int max_iter, float s0, float& s, HelixPt& h,
-                                                int& iters) {
+                                                int& iters, bool have_first = false) {
     const float inv2R = 0.5f / R;
     const float invR = 1.0f / R;
     s = s0;
     for (int it = 0; it < max_iter; ++it) {
-        helix_at(x, y, cphi, sphi, w, s, h);
+        if (!(have_first && it == 0)) helix_at(x, y, cphi, sphi, w, s, h);
         float f = (fmaf(h.x, h.x, h.y * h.y) - R * R) * inv2R;
         iters = it + 1;
         if (fabsf(f) <= tol) return true;
         float fp = (h.x * h.cp + h.y * h.sp) * invR;
-        float ds = f / fp;
-        float sn = s - ds;
-        s = sn > 0.0f ? sn : 0.5f * s;   // keep the path positive
+        s -= f / fp;
     }
     return false;
 }
@@ -321,6 +377,76 @@ __device__ __forceinline__ bool inv3_spd(const T s[6], T inv[6], T tau) {
     return true;
 }
 
+// Full update in FP64 for an ill-conditioned S (the FP32 test failed).
+// When S is ill-conditioned the update shrinks some variances by orders of
+// magnitude in one step, and FP32 products of the gain would lose the digits
+// an FP64 inverse keeps; so this path also forms the gain and the Joseph
+// covariance in FP64.  Kept out of line, with loops over small arrays, so its
+// registers do not weigh on the FP32 path that runs almost always.
+__device__ __noinline__ uint32_t kalman_update_fp64(float* p, float* c, const float* m, const float* V,
+                                                    float chi2_cut, float* chi2) {
+    double C[6][6], Vd[3][3], S[6], Si[6], K[6][3], A[6][6], M[6][6];
+#pragma unroll 1
+    for (int i = 0; i < 6; ++i)
+#pragma unroll 1
+        for (int j = 0; j < 6; ++j) C[i][j] = (double)c[I21(i, j)];
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i)
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) Vd[i][j] = (double)V[I21(i, j)];
+    S[0] = C[0][0] + Vd[0][0]; S[1] = C[1][0] + Vd[1][0]; S[2] = C[1][1] + Vd[1][1];
+    S[3] = C[2][0] + Vd[2][0]; S[4] = C[2][1] + Vd[2][1]; S[5] = C[2][2] + Vd[2][2];
+    if (!inv3_spd<double>(S, Si, PD_TAU64)) return ST_S_NOT_PD;
+    double Sm[3][3] = {{Si[0], Si[1], Si[3]}, {Si[1], Si[2], Si[4]}, {Si[3], Si[4], Si[5]}};
+    double r[3], w[3], c2 = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) r[i] = (double)m[i] - (double)p[i];
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+        w[i] = Sm[i][0] * r[0] + Sm[i][1] * r[1] + Sm[i][2] * r[2];
+        c2 += r[i] * w[i];
+    }
+    if (chi2_cut > 0.0f && c2 > (double)chi2_cut) return ST_CHI2_CUT;
+    *chi2 = (float)c2;
+#pragma unroll 1
+    for (int i = 0; i < 6; ++i) {
+        double dp = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            K[i][j] = C[i][0] * Sm[0][j] + C[i][1] * Sm[1][j] + C[i][2] * Sm[2][j];
+            dp += C[i][j] * w[j];
+        }
+        p[i] = (float)((double)p[i] + dp);
+    }
+#pragma unroll 1
+    for (int i = 0; i < 6; ++i)
+#pragma unroll 1
+        for (int j = 0; j < 6; ++j) A[i][j] = (i == j ? 1.0 : 0.0) - (j < 3 ? K[i][j] : 0.0);
+#pragma unroll 1
+    for (int i = 0; i < 6; ++i)
+#pragma unroll 1
+        for (int l = 0; l < 6; ++l) {
+            double a = 0.0;
+#pragma unroll 1
+            for (int k = 0; k < 6; ++k) a += A[i][k] * C[k][l];
+            M[i][l] = a;
+        }
+#pragma unroll 1
+    for (int i = 0; i < 6; ++i)
+#pragma unroll 1
+        for (int l = 0; l <= i; ++l) {
+            double a = 0.0;
+#pragma unroll 1
+            for (int k = 0; k < 6; ++k) a += M[i][k] * A[l][k];
+#pragma unroll 1
+            for (int j = 0; j < 3; ++j)
+#pragma unroll 1
+                for (int k = 0; k < 3; ++k) a += K[i][j] * Vd[j][k] * K[l][k];
+            c[I21(i, l)] = (float)a;
+        }
+    return 0;
+}
+
 // Update of state st (already propagated to the surface) with hit m, V.
 //   S = C'_pos + V;  w = S^-1 r;  chi2 = r . w;  K = C' H^T S^-1 (6x3);
 //   p+ = p' + C' H^T w;
@@ -329,9 +455,12 @@ __device__ __forceinline__ bool inv3_spd(const T s[6], T inv[6], T tau) {
 // carries no cancellation, while A C' A^T is second order in the (small)
 // rows of A along the measured directions, so the posterior keeps close to
 // FP32 relative accuracy even when the update shrinks C' by orders of
-// magnitude.
+// magnitude.  When the FP32 positive-definiteness test of S fails:
+// fp64_fallback 1 inverts S in FP64 and continues in FP32; 3 runs the whole
+// update in FP64 (kalman_update_fp64); 0 skips the update.  Mode 2 runs the
+// FP64 update for every surface (testing).
 // Returns 0, or ST_S_NOT_PD / ST_CHI2_CUT when the update is skipped;
-// ST_FP64_FALLBACK is OR-ed into *flags when the FP64 inversion ran.
+// ST_FP64_FALLBACK is OR-ed into *flags when an FP64 path ran.
 __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], const float V[6],
                                                   const Params& P, float& chi2, uint32_t& flags) {
     float* c = st.c;
@@ -339,13 +468,14 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
     float Si[6];
     if (P.fp64_fallback == 2 || !inv3_spd<float>(S, Si, PD_TAU32)) {
         if (!P.fp64_fallback) return ST_S_NOT_PD;
+        flags |= ST_FP64_FALLBACK;
+        if (P.fp64_fallback != 1) return kalman_update_fp64(st.p, st.c, m, V, P.chi2_cut, &chi2);
         double Sd[6], Sid[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) Sd[k] = (double)c[k] + (double)V[k];
         if (!inv3_spd<double>(Sd, Sid, PD_TAU64)) return ST_S_NOT_PD;
 #pragma unroll
         for (int k = 0; k < 6; ++k) Si[k] = (float)Sid[k];
-        flags |= ST_FP64_FALLBACK;
     }
     float r0 = m[0] - st.p[0], r1 = m[1] - st.p[1], r2 = m[2] - st.p[2];
     float w0 = Si[0] * r0 + Si[1] * r1 + Si[3] * r2;
@@ -422,7 +552,8 @@ __device__ __forceinline__ bool bad_input(const State& st) {
 }
 
 // --------------------------------------------------------- one layer step
-// Cylinder of radius R.  Returns the status flags of the layer; on success
+// Cylinder of radius R.  s_start: proposed path length, or NaN for the
+// straight-line start.  Returns the status flags of the layer; on success
 // the state is updated and *updated set.
 struct StepOut {
     uint32_t flags;
@@ -431,7 +562,8 @@ struct StepOut {
 };
 
 __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float m[3], const float V[6],
-                                                 const Params& P, float& chi2, float tol, float s_start) {
+                                                 const Params& P, float& chi2, float tol, float s_start,
+                                                 float accept_cm = 0.0f) {
     StepOut o{0u, false, 0};
     if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
     float x = st.p[0], y = st.p[1];
@@ -440,13 +572,39 @@ __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float
     float kq = -st.q * KAPPA * P.bz;
     float w = kq * st.p[3];
     if (!cylinder_reachable(x, y, cphi, sphi, w, R)) { o.flags = ST_NO_CROSSING; return o; }
-    float s0 = s_start > 0.0f ? s_start : line_path(x, y, cphi, sphi, R);
-    if (!(s0 > 0.0f)) s0 = fabsf(R - sqrtf(fmaf(x, x, y * y)));
+    // start: the proposal, else the straight-line root; the closed form when
+    // neither exists or when Newton ends outside the crossing window.  A
+    // proposal is kept when its own residual |r(s0) - R| is at most
+    // accept_cm (that evaluation is Newton's first); otherwise the plain
+    // start is used and ML_REJECTED set.
+    bool line_ok = true;
     HelixPt h;
     float s;
-    if (!newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, s0, s, h, o.iters)) {
-        o.flags = ST_NEWTON_FAIL;
-        return o;
+    float s0 = s_start;
+    bool have_first = false;
+    int pre = 0;
+    if (!isnan(s_start)) {
+        helix_at(x, y, cphi, sphi, w, s_start, h);
+        const float f0 = (fmaf(h.x, h.x, h.y * h.y) - R * R) * (0.5f / R);
+        have_first = fabsf(f0) <= accept_cm && s_start > -BACK_TOL;
+        if (!have_first) {
+            o.flags |= ST_ML_REJECTED;
+            pre = 1;
+        }
+    }
+    if (!have_first) {
+        s0 = line_path(x, y, cphi, sphi, R, &line_ok);
+        if (!line_ok && !closed_form_cylinder(x, y, cphi, sphi, w, R, s0)) { o.flags |= ST_NO_CROSSING; return o; }
+    }
+    bool conv = newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, s0, s, h, o.iters, have_first);
+    o.iters += pre;
+    if (!conv || !(s > -BACK_TOL) || fabsf(w * s) > PI_F) {
+        float sc;
+        if (!closed_form_cylinder(x, y, cphi, sphi, w, R, sc)) { o.flags |= ST_NO_CROSSING; return o; }
+        int it2 = 0;
+        conv = newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, sc, s, h, it2);
+        o.iters += it2;
+        if (!conv || !(s > -BACK_TOL) || fabsf(w * s) > PI_F) { o.flags |= ST_NEWTON_FAIL; return o; }
     }
     float sinth, costh;
     sincosf(st.p[5], &sinth, &costh);
@@ -473,12 +631,12 @@ __device__ __forceinline__ StepOut step_plane(State& st, float Z, const float m[
     float sinth, costh;
     sincosf(st.p[5], &sinth, &costh);
     float tanth = sinth / costh;
-    float s = (Z - st.p[2]) * tanth;
-    if (!(s > 0.0f)) { o.flags = ST_NO_CROSSING; return o; }
-    float sphi, cphi;
-    sincosf(st.p[4], &sphi, &cphi);
+    float s = (Z - st.p[2]) * tanth;     // ahead (or at most BACK_TOL behind), within half a turn
     float kq = -st.q * KAPPA * P.bz;
     float w = kq * st.p[3];
+    if (!(s > -BACK_TOL) || !(fabsf(w * s) <= PI_F)) { o.flags = ST_NO_CROSSING; return o; }
+    float sphi, cphi;
+    sincosf(st.p[4], &sphi, &cphi);
     HelixPt h;
     helix_at(st.p[0], st.p[1], cphi, sphi, w, s, h);
     Jac J;

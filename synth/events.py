@@ -272,6 +272,13 @@ def simulate_to_cylinder(par, q, R, bz=B_TESLA, max_path=400.0):
 
     par: (n,6) track parameters; R: (n,) radii.  NaN when not reached.
     """
+    par = np.asarray(par, dtype=np.float64)
+    R = np.broadcast_to(np.asarray(R, dtype=np.float64), (par.shape[0],))
+    q = np.broadcast_to(np.asarray(q, dtype=np.float64), (par.shape[0],))
+    return _chunked(lambda p, qq, rr: (_simulate_to_cylinder(p, qq, rr, bz, max_path),), (par, q, R))[0]
+
+
+def _simulate_to_cylinder(par, q, R, bz, max_path):
     n = par.shape[0]
     sim = _Sim(par[:, 0], par[:, 1], par[:, 2], par[:, 4], par[:, 5], 1.0 / par[:, 3], q, bz)
     out = np.full(n, np.nan)
@@ -402,8 +409,9 @@ def make_ragged_event(cfg: EventConfig = RAGGED, n_tracks: int | None = None):
     +-extra['disks'] (r <= rmax).  Walking the truth trajectory, the
     surfaces are taken in the order they are crossed (outward barrels not yet
     crossed, disks on the side the particle moves to), up to L ~ U{lmin..lmax}
-    per track; the walk stops early when the particle leaves the volume or
-    has travelled 400 cm transversely.  A fraction of hits are outliers:
+    per track; the walk stops early when the particle leaves the volume, or
+    when it has turned by half a turn since its last surface (a looper, which
+    the fit does not follow either).  A fraction of hits are outliers:
     the crossing moved uniformly within +-outlier_half cm in the surface's
     local coordinates (r-phi arc and z on cylinders, x and y on planes),
     with the hit covariance unchanged.
@@ -430,6 +438,8 @@ def make_ragged_event(cfg: EventConfig = RAGGED, n_tracks: int | None = None):
     s_val = np.zeros((n, Lmax))
     s_state = np.full((n, Lmax, 6), np.nan)
     alive = np.ones(n, dtype=bool)
+    last = np.zeros(n)                      # transverse path at the last recorded surface
+    half_turn = np.pi * tr["pt"] / (KAPPA * B_TESLA)
     while True:
         idx = np.nonzero(alive)[0]
         if idx.size == 0:
@@ -478,9 +488,10 @@ def make_ragged_event(cfg: EventConfig = RAGGED, n_tracks: int | None = None):
             s_val[iv, slot] = np.where(tb[valid], Rb[e][valid], Zd[e][valid])
             s_state[iv, slot] = _state_of(se[:, valid], sim.ipt[iv], sim.theta[iv])
             cnt[iv] += 1
+            last[iv] = sim.path[iv]
             kb[ie[tb]] += 1
             kd[ie[~tb]] += 1
-        done = (cnt >= Lwant) | ((kb >= nb) & (kd >= nd)) | (sim.path > 400.0)
+        done = (cnt >= Lwant) | ((kb >= nb) & (kd >= nd)) | (sim.path - last > half_turn)
         done |= (np.hypot(sim.s[0], sim.s[1]) > rmax) & (np.abs(sim.s[2]) > zmax)
         alive &= ~done
     # CSR

@@ -22,7 +22,7 @@ def test_opts_default_and_version():
     o = _lib.default_opts()
     assert o.bz_tesla == pytest.approx(3.8)
     assert o.newton_tol_cm == pytest.approx(1e-6)
-    assert o.newton_max_iter == 8 and o.fp64_fallback == 1 and o.width == 0 and not o.mlp
+    assert o.newton_max_iter == 8 and o.fp64_fallback == 3 and o.width == 0 and not o.mlp
     assert p2r.library().p2r_version().startswith(b"p2r-mi355x")
 
 

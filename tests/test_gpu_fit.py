@@ -152,29 +152,57 @@ def test_edge_cases_status(ctx):
     assert np.all(g["par"][1, 1:] == d["par"][1, 1:].astype(np.float32))
 
 
-def test_fp64_inversion_forced_matches(ctx):
+def test_fp64_update_forced_matches(ctx):
+    """The FP64 update path (inverse, gain, Joseph covariance), forced on every surface."""
     d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=512)
     g = run_p2r(ctx, d, 64, fp64_fallback=2)
     r = oracle.fit_event(d, "barrel")
     compare(g, r, ctx="forced fp64")
     assert np.all(g["status"] & p2r.ST_FP64_FALLBACK)
+    dz = ev.make_disk_event(ev.P2Z_THROUGHPUT, n_tracks=512)
+    compare(run_p2z(ctx, dz, fp64_fallback=2), oracle.fit_event(dz, "disk"), ctx="forced fp64 p2z")
 
 
 def test_fp64_fallback_triggers_on_ill_conditioned_S(ctx):
-    """A hit 1e-4 as wide radially as tangentially makes the FP32 test fail and the FP64 inversion run."""
-    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=64)
+    """On the first layer (r = 4 cm) a hit 2e-8 cm^2 wide along the layer normal and 1e-4
+    along the layer gives S a condition number ~5e5: the FP32 test fails and the update
+    runs in FP64, matching the oracle.  (The layer is the innermost one so that the FP32
+    position quantum, ulp(4 cm) = 4.8e-7 cm, stays far below the hit's 1.4e-4 cm.)"""
+    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=256)
+    li = 0
+    tr = d["truth"][:, li, :3]
+    ok = np.isfinite(tr[:, 0])
+    nrm = np.zeros((256, 2))
+    nrm[ok] = tr[ok, :2] / np.hypot(tr[ok, 0], tr[ok, 1])[:, None]
+    tng = np.stack([-nrm[:, 1], nrm[:, 0]], 1)
+    vrr, vtt = 2e-8, 1e-4
+    Vxy = vrr * nrm[:, :, None] * nrm[:, None, :] + vtt * tng[:, :, None] * tng[:, None, :]
+    g0 = np.random.default_rng(9)
+    hits = d["hits"].copy()
     hc = d["hitcov"].copy()
-    hc[:, 5, 0] = hc[:, 5, 2] = 2e-9    # x, y variance of layer 5 tiny; z unchanged
-    e = dict(d, hitcov=hc)
-    g = run_p2r(ctx, e, 64)
+    hits[ok, li, :2] = tr[ok, :2] + nrm[ok] * g0.normal(0, np.sqrt(vrr), (ok.sum(), 1)) \
+        + tng[ok] * g0.normal(0, np.sqrt(vtt), (ok.sum(), 1))
+    hc[:, li, 0], hc[:, li, 1], hc[:, li, 2] = Vxy[:, 0, 0], Vxy[:, 1, 0], Vxy[:, 1, 1]
+    e = dict(d, hits=hits.astype(np.float32).astype(np.float64), hitcov=hc.astype(np.float32).astype(np.float64))
     r = oracle.fit_event(e, "barrel")
+    g = run_p2r(ctx, e, 64)                     # default: whole update in FP64 on fallback
     st = g["status"]
-    assert (st & p2r.ST_FP64_FALLBACK).mean() > 0.5
-    assert np.all(np.isfinite(g["par"]))
-    # FP32 arithmetic around an S with condition ~1e6: agreement at 1e-3 of the parameters
-    dpar = np.abs(g["par"] - r["par"])
-    dpar[:, 4] = np.abs(np.angle(np.exp(1j * (g["par"][:, 4] - r["par"][:, 4]))))
-    assert np.all(dpar <= 1e-3 * np.maximum(np.abs(r["par"]), [1, 1, 1, 0, 1, 0]) + 1e-6)
+    assert (st[ok] & p2r.ST_FP64_FALLBACK).mean() > 0.9
+    # With S this ill-conditioned the limit is no longer the update: the FP32 Jacobian
+    # leaves C' a ~1e-8 relative component (~1e-10 cm^2) along the layer normal, which
+    # a 2e-8 cm^2 hit resolves, moving that hit's chi2 term by ~0.5 %.  Bounds: 1e-3
+    # relative on the parameters, 1e-2 on chi2.
+    g1 = run_p2r(ctx, e, 64, fp64_fallback=1)
+    assert (g1["status"][ok] & p2r.ST_FP64_FALLBACK).mean() > 0.9
+    errs = {}
+    for name, x in (("full FP64 update", g), ("FP64 inverse only", g1)):
+        assert np.all(np.isfinite(x["par"]))
+        dpar = np.abs(x["par"] - r["par"])
+        dpar[:, 4] = np.abs(np.angle(np.exp(1j * (x["par"][:, 4] - r["par"][:, 4]))))
+        rel = dpar / np.maximum(np.abs(r["par"]), [1, 1, 1, 1e-30, 1, 1e-30])
+        errs[name] = (rel.max(), (np.abs(x["chi2"] - r["chi2"]) / np.maximum(r["chi2"], 1)).max())
+        print(name, "max rel par %.2e  max rel chi2 %.2e" % errs[name], flush=True)
+    assert errs["full FP64 update"][0] < 1e-3 and errs["full FP64 update"][1] < 1e-2
 
 
 def test_empty_and_argument_errors(ctx):

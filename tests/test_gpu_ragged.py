@@ -1,0 +1,141 @@
+"""GPU parity of the ragged batched fit (CSR surfaces, persistent kernel, HIP graph)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2401_14221_amd as p2r
+from synth import events as ev
+
+from .parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = p2r.Context(0)
+    yield c
+    c.close()
+
+
+def upload(d, dev="cuda"):
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    return dict(offsets=torch.as_tensor(d["offsets"], dtype=torch.int64, device=dev),
+                surf_type=torch.as_tensor(d["surf_type"], dtype=torch.uint8, device=dev),
+                surf_val=f(d["surf_val"]), hit_pos=f(d["hits"]), hit_cov=f(d["hitcov"]),
+                par_in=f(d["par"]), cov_in=f(d["cov"]),
+                q=torch.as_tensor(d["q"], dtype=torch.int8, device=dev))
+
+
+# the ragged workload carries 5 % outliers up to 1 cm (~100 sigma) away: its
+# fits reject hits with chi2 > 30 (per hit), on the GPU and in the oracle
+CUT = 30.0
+
+
+def run(ctx, u, n_hits, lmax=25, out=None, stream=None, **kw):
+    kw.setdefault("chi2_cut", CUT)
+    po, co, c2, st = ctx.fit_tracks_batched(u["offsets"], u["surf_type"], u["surf_val"], u["hit_pos"],
+                                            u["hit_cov"], u["par_in"], u["cov_in"], u["q"], n_hits, lmax,
+                                            out=out, stream=stream, **kw)
+    torch.cuda.synchronize()
+    return dict(par=po.cpu().numpy(), cov=co.cpu().numpy(), chi2=c2.cpu().numpy(),
+                status=st.cpu().numpy().view(np.uint32))
+
+
+def test_ragged_parity_small(ctx):
+    d = ev.make_ragged_event(ev.RAGGED, n_tracks=20000)
+    u = upload(d)
+    H = int(d["offsets"][-1])
+    r = oracle.fit_ragged(d, chi2_cut=CUT)
+    s = torch.cuda.Stream()
+    for use_graph in (0, 1):
+        g = run(ctx, u, H, stream=s, use_graph=use_graph)
+        rep = compare(g, r, ctx=f"ragged graph={use_graph}")
+        print("ragged", use_graph, rep, flush=True)
+    L = np.diff(d["offsets"])
+    assert np.all(((g["status"] >> 8) & 0xFF) <= L)
+
+
+def test_ragged_graph_replays_match_eager(ctx):
+    """Replays of the captured graph, with unrelated eager work between them, equal the eager launch bit for bit."""
+    d = ev.make_ragged_event(ev.RAGGED.with_(seed=55), n_tracks=5000)
+    u = upload(d)
+    H = int(d["offsets"][-1])
+    s = torch.cuda.Stream()
+    ref = run(ctx, u, H, stream=s, use_graph=0)
+    outs = (torch.empty((5000, 6), device="cuda"), torch.empty((5000, 21), device="cuda"),
+            torch.empty(5000, device="cuda"), torch.zeros(5000, dtype=torch.int32, device="cuda"))
+    for rep in range(4):
+        outs[3].zero_()
+        with torch.cuda.stream(s):
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()
+        g = run(ctx, u, H, out=outs, stream=s, use_graph=1)
+        for k in ("par", "cov", "chi2"):
+            assert np.array_equal(g[k], ref[k]), (rep, k)
+        assert np.array_equal(g["status"], ref["status"])
+        torch.cuda.synchronize()
+
+
+def test_ragged_new_arguments_recapture(ctx):
+    s = torch.cuda.Stream()
+    for n, seed in ((3000, 11), (1200, 12), (3000, 11)):
+        d = ev.make_ragged_event(ev.RAGGED.with_(seed=seed), n_tracks=n)
+        u = upload(d)
+        g = run(ctx, u, int(d["offsets"][-1]), stream=s)
+        compare(g, oracle.fit_ragged(d, chi2_cut=CUT), ctx=f"recapture n={n}")
+
+
+def test_ragged_edge_cases(ctx):
+    d = ev.make_ragged_event(ev.RAGGED.with_(seed=21), n_tracks=300)
+    # track 5 without surfaces: drop its hits from the CSR
+    L = np.diff(d["offsets"])
+    keep = np.ones(int(d["offsets"][-1]), bool)
+    keep[d["offsets"][5]:d["offsets"][6]] = False
+    L[5] = 0
+    off = np.concatenate([[0], np.cumsum(L)])
+    st = d["surf_type"][keep].copy()
+    st[off[10]] = 7                        # unknown surface type on track 10
+    e = dict(d, offsets=off, surf_type=st, surf_val=d["surf_val"][keep], hits=d["hits"][keep],
+             hitcov=d["hitcov"][keep])
+    u = upload(e)
+    H = int(off[-1])
+    g = run(ctx, u, H, lmax=25)
+    r = oracle.fit_ragged(e, chi2_cut=CUT)
+    compare(g, r, ctx="ragged edge")
+    assert (g["status"][5] >> 8) & 0xFF == 0 and g["status"][5] & p2r.ST_DONE
+    assert g["status"][10] & p2r.ST_BAD_INPUT
+    # a track longer than max_surfaces is rejected as a whole
+    L = np.diff(off)
+    lm = int(L.max()) - 1
+    g2 = run(ctx, u, H, lmax=lm)
+    long_ = L > lm
+    assert np.all(g2["status"][long_] & p2r.ST_BAD_INPUT)
+    assert np.all(g2["status"] & p2r.ST_DONE)
+    with pytest.raises(p2r.P2RError):
+        run(ctx, u, H, lmax=300)
+    empty = ctx.fit_tracks_batched(u["offsets"][:1], u["surf_type"], u["surf_val"], u["hit_pos"], u["hit_cov"],
+                                   u["par_in"][:0], u["cov_in"][:0], u["q"][:0], 0, 25)
+    assert empty[0].numel() == 0
+
+
+def test_ragged_full_size_sampled(ctx):
+    """1,000,000 tracks with 5..25 mixed surfaces in one graph launch; every track processed exactly once."""
+    d = ev.make_ragged_event(ev.RAGGED)
+    u = upload(d)
+    H = int(d["offsets"][-1])
+    n = d["par"].shape[0]
+    s = torch.cuda.Stream()
+    g = run(ctx, u, H, stream=s)
+    st = g["status"]
+    assert np.all(st & p2r.ST_DONE)
+    rng = np.random.default_rng(3)
+    idx = np.sort(rng.choice(n, 8000, replace=False))
+    sub_off = np.concatenate([[0], np.cumsum(np.diff(d["offsets"])[idx])])
+    hsel = np.concatenate([np.arange(d["offsets"][i], d["offsets"][i + 1]) for i in idx])
+    sub = dict(offsets=sub_off, surf_type=d["surf_type"][hsel], surf_val=d["surf_val"][hsel],
+               hits=d["hits"][hsel], hitcov=d["hitcov"][hsel], par=d["par"][idx], cov=d["cov"][idx], q=d["q"][idx])
+    r = oracle.fit_ragged(sub, chi2_cut=CUT)
+    rep = compare({k: v[idx] for k, v in g.items()}, r, ctx="ragged full")
+    print("ragged full sampled", rep, flush=True)

@@ -146,11 +146,58 @@ def test_cylinder_vs_bisection(orc):
         assert s == pytest.approx(0.5 * (lo + hi), abs=1e-10)
 
 
+def _bisect_path(p, q, R, lo, hi):
+    """Root of |xy(s)| = R in [lo, hi] by bisection over the helix map."""
+    f = lambda s: np.hypot(*oracle.helix(p, q, B, s)[:2]) - R  # noqa: E731
+    flo = f(lo)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if (f(mid) < 0) == (flo < 0):
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def test_crossing_rule_backward_step_and_half_turn(orc):
+    """The next crossing is the smallest s > -1 cm among the crossings within half a turn.
+
+    A state 0.3 cm beyond the layer, moving out, is taken back to it (bisection on
+    the helix gives the same s < 0); 3 cm beyond, no crossing lies within half a
+    turn; a start 0.12 cm off the axis and pointing inward still crosses forward.
+    """
+    for q in (1.0, -1.0):
+        R = 40.0
+        p = np.array([R + 0.3, 0.0, 0.0, 1 / 5.0, 0.2, 1.0])
+        s = oracle.path(p, q, B, 0, R)
+        assert -1.0 < s < 0.0
+        assert s == pytest.approx(_bisect_path(p, q, R, -1.0, 0.0), abs=1e-10)
+        p3 = np.array([R + 3.0, 0.0, 0.0, 1 / 5.0, 0.2, 1.0])
+        assert oracle.path(p3, q, B, 0, R) is None
+        pv = np.array([0.12, 0.0, 0.0, 1 / 2.0, np.pi - 0.3, 1.0])
+        s = oracle.path(pv, q, B, 0, 2.5)
+        assert s > 0 and s == pytest.approx(_bisect_path(pv, q, 2.5, 0.0, 3.0), abs=1e-10)
+    # planes: 0.5 cm behind is reached backwards, 2 cm behind is not a crossing
+    p = np.array([1.0, 2.0, 100.5, 0.5, 0.3, 0.5])
+    s = oracle.path(p, 1.0, B, 1, 100.0)
+    assert s == pytest.approx(-0.5 * np.tan(0.5), rel=1e-14)
+    assert oracle.path(np.array([1.0, 2.0, 105.0, 0.5, 0.3, 0.5]), 1.0, B, 1, 100.0) is None
+    # a plane more than half a turn ahead (a looper spiralling along z) is not the next surface
+    pt = 0.6
+    half = np.pi * pt / (KAPPA * B)
+    th = np.arctan2(1.0, 1.0 / (1.1 * half / 100.0))        # reaches z = 100 after 1.1 half turns
+    assert oracle.path(np.array([0.0, 0.0, 0.0, 1 / pt, 0.0, th]), 1.0, B, 1, 100.0) is None
+    th = np.arctan2(1.0, 1.0 / (0.9 * half / 100.0))
+    assert oracle.path(np.array([0.0, 0.0, 0.0, 1 / pt, 0.0, th]), 1.0, B, 1, 100.0) == pytest.approx(0.9 * half)
+
+
 def test_crossings_match_independent_rk4_simulation(orc):
     """Oracle path lengths to cylinders and planes agree with the generator's RK4 of the Lorentz force."""
     g = np.random.default_rng(5)
     n = 300
     par = np.array([rstate(g, r0=(0, 5))[0] for _ in range(n)])
+    # moving outward, so the next crossing is the first forward one the simulation finds
+    par[:, 4] = np.arctan2(par[:, 1], par[:, 0]) + g.uniform(-1.2, 1.2, n)
     q = np.where(g.random(n) < 0.5, -1.0, 1.0)
     R = g.uniform(10.0, 80.0, n)
     s_rk4 = ev.simulate_to_cylinder(par, q, R)
@@ -298,7 +345,7 @@ def test_fit_rotation_and_mirror_symmetry(orc):
         T[:2, :2] = Rm
         Cexp = T @ ev.unpack21(out["cov"]) @ T.T
         assert o2["chi2"] == pytest.approx(out["chi2"], rel=1e-8)
-        assert o2["par"][:, :2] == pytest.approx(out["par"][:, :2] @ Rm.T, abs=1e-8)
+        assert o2["par"][:, :2] == pytest.approx(out["par"][:, :2] @ Rm.T, rel=1e-9, abs=1e-8)
         assert ev.unpack21(o2["cov"]) == pytest.approx(Cexp, abs=1e-12)
     # charge conjugation + mirror y -> -y
     M = np.diag([1, -1, 1, 1, -1, 1.0])
