@@ -28,7 +28,7 @@ HBM_PEAK_GBPS = 8000.0
 # FP32 vector peak of MI355X (published; counts an FMA as 2 flops)
 FP32_PEAK_TFLOPS = 157.3
 # algorithmic work per track-layer ("Roofline of the fit kernel")
-P2R_FLOP_PER_TL = 1117.0
+P2R_FLOP_PER_TL = 1261.0
 P2Z_FLOP_PER_TL = 930.0
 TRACK_BYTES = 28 * 4 * 2 + 4 + 4      # record in + record out + chi2 + status
 HIT_BYTES = 9 * 4
@@ -42,7 +42,32 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="headline p2r figure only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; profiles carry it so stale counter data is not reported."""
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2401_14221_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the p2r fit kernel from the committed counter profile, if current."""
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "p2r_fit_traffic.json")
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def log(*a):
@@ -118,7 +143,7 @@ def main():
                    "layers": L, "track_layers": tl, "width": W, "variant": ctx.variant_name(0),
                    "parallelism": "one lane per track, one GPU"},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": tflops / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "kernel": ctx.variant_name(0), "flop_per_track_layer": P2R_FLOP_PER_TL},
         "hbm": {"achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
                 "bytes_per_launch": alg_bytes},
@@ -128,6 +153,13 @@ def main():
                 "newton_fail_tracks": int(((st & p2r.ST_NEWTON_FAIL) != 0).sum()),
                 "wall_ms_per_step": wall_ms},
     }
+    res["config"]["kernel_source_hash"] = kernel_source_hash()
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     del trk, hits, out
     if not args.no_extra:
         res["extra"] = extra_legs(ctx, args, stream, ev, p2r, dev)

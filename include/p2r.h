@@ -26,8 +26,10 @@
  *  - Per-track numerical problems are never errors: they are reported in the
  *    status word (P2R_ST_* bits below) and the track keeps its last state.
  *  - The library allocates device memory only in p2r_ctx_create,
- *    p2r_mlp_create and, once per shape, in fit_tracks_batched (its
- *    workspace and graph); everything is released by the matching destroy.
+ *    p2r_autotune (temporaries), p2r_mlp_create, p2r_mlp_grads/train_step
+ *    (gradient partials, when the batch grows) and fit_tracks_batched (its
+ *    workspace, when the problem grows, and one graph per argument set);
+ *    everything is released by the matching destroy.
  *
  * Status word per track: bits 0..7 flags, bits 8..15 the number of surfaces
  * whose update was applied, bit 31 set when the track was processed.
@@ -71,7 +73,7 @@ typedef struct p2r_ctx p2r_ctx; /* opaque: device, tuned variants, workspace, gr
 
 /* Fit options.  p2r_opts_default() fills: bz 3.8 T, newton_tol 1e-6 cm,
  * 8 iterations, chi2 cut off, FP64 fallback 3, width 0 (tuned/default),
- * no MLP, graphs on. */
+ * no MLP, graphs on, straight-line start. */
 typedef struct {
     float bz_tesla;          /* field along +z */
     float newton_tol_cm;     /* |r(s) - R| tolerance, raised to 2 ulp(R) */
@@ -87,6 +89,9 @@ typedef struct {
                                 graph (needs a non-NULL stream); 0 = launch the kernels directly */
     unsigned long long* helix_evals; /* nullable device counter: p2r adds the number of helix
                                 evaluations of its cylinder solves (diagnostics) */
+    int32_t cyl_start;       /* start of the helix-to-cylinder Newton iteration without an MLP:
+                                0 = straight-line path (plain), 1 = closed-form FP32 crossing
+                                (t = tan(omega s / 2) quadratic), which Newton then only checks */
 } p2r_opts;
 
 void p2r_opts_default(p2r_opts* o);
@@ -166,7 +171,7 @@ const char* p2r_variant_name(p2r_ctx* ctx, int which);
  * matrix cores and FP32 accumulation, that proposes the starting path length
  * of the helix-to-cylinder Newton iteration.  Input: 7 features of the state
  * and the target radius R (p2r_mlp_features); output y with the proposal
- * s0 = s_line (1 + y / 100), s_line the straight-line path.  The iteration
+ * s0 = s_line (1 + sinh(y) / 100), s_line the straight-line path.  The iteration
  * refines s0, and rejects it (ML_REJECTED, plain start) when |r(s0) - R| >
  * 1e-3 cm.  Parameters: one flat FP32 vector of p2r_mlp_n_params() = 4737
  * values, W1 [64][7], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 [1]
@@ -180,12 +185,14 @@ int p2r_mlp_n_params(void);
 /* host_params: host array of p2r_mlp_n_params() floats; resets Adam; synchronises. */
 int p2r_mlp_set_params(p2r_mlp* mlp, const float* host_params);
 int p2r_mlp_get_params(p2r_mlp* mlp, float* host_params);
-/* Features x [n][7] (and, with s_label [n], targets t [n] = 100 (s_label / s_line - 1);
+/* Features x [n][7] (and, with s_label [n], targets t [n] = asinh(100 (s_label / s_line - 1));
  * s_line [n] nullable) of states par [n][6], charges q [n] (+-1.0f) and radii R [n]. */
 int p2r_mlp_features(p2r_mlp* mlp, const p2r_opts* opts, int32_t n, const float* par, const float* q,
                      const float* R, const float* s_label, float* x, float* t, float* s_line, void* stream);
 int p2r_mlp_forward(p2r_mlp* mlp, const float* x, float* y, int32_t B, void* stream);
-/* Gradients of the mean squared error over the batch (grads_out [n_params], loss_out [1]; nullable). */
+/* Gradients of the mean squared error over the batch (grads_out [n_params], loss_out [1]; nullable).
+ * Deterministic (per-workgroup partials summed in a fixed order); the partial
+ * buffer is allocated on the first call and grown when B grows. */
 int p2r_mlp_grads(p2r_mlp* mlp, const float* x, const float* t, int32_t B, float* grads_out,
                   float* loss_out, void* stream);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights, then a fresh BF16 copy. */

@@ -17,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 KAPPA = 2.99792458e-3
-TARGET_SCALE = 100.0          # the network predicts 100 * (s / s_line - 1)
+TARGET_SCALE = 100.0          # the network predicts asinh(100 * (s / s_line - 1))
 
 
 def bf16_round(a):
@@ -105,8 +105,9 @@ def features(par, q, R, bz=3.8):
 
 
 def target(s, sline):
-    return TARGET_SCALE * (np.asarray(s) / sline - 1.0)
+    """asinh(100 (s / s_line - 1)): linear near 0, logarithmic in the rare large tails."""
+    return np.arcsinh(TARGET_SCALE * (np.asarray(s) / sline - 1.0))
 
 
 def proposal(y, sline):
-    return sline * (1.0 + np.asarray(y) / TARGET_SCALE)
+    return sline * (1.0 + np.sinh(np.asarray(y)) / TARGET_SCALE)

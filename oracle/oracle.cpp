@@ -371,7 +371,8 @@ void fit_one(const FitArgs& a, int64_t t) {
     uint32_t st = 0;
     double chi2 = 0.0;
     int32_t nused = 0;
-    if (bad_input(p, a.cov + t * 21)) {
+    const bool rejected = bad_input(p, a.cov + t * 21);
+    if (rejected) {
         st |= ST_BAD_INPUT;
     } else {
         for (int64_t h = a.offsets[t]; h < a.offsets[t + 1]; ++h) {
@@ -415,7 +416,7 @@ void fit_one(const FitArgs& a, int64_t t) {
     }
     for (int i = 0; i < 6; ++i) a.par_out[t * 6 + i] = p[i];
     pack(C, a.cov_out + t * 21);
-    if (st & ST_BAD_INPUT) for (int i = 0; i < 21; ++i) a.cov_out[t * 21 + i] = a.cov[t * 21 + i];
+    if (rejected) for (int i = 0; i < 21; ++i) a.cov_out[t * 21 + i] = a.cov[t * 21 + i];
     a.chi2_out[t] = chi2;
     a.nused_out[t] = nused;
     a.status_out[t] = st | ST_DONE;

@@ -138,6 +138,7 @@ p2r::Params params_of(const p2r_opts* o) {
     P.max_iter = o->newton_max_iter;
     P.chi2_cut = o->chi2_cut;
     P.fp64_fallback = o->fp64_fallback;
+    P.start_mode = o->cyl_start;
     return P;
 }
 
@@ -148,6 +149,7 @@ int check_opts(const p2r_opts* o) {
     if (o->newton_max_iter < 1 || o->newton_max_iter > 64) return fail(P2R_EINVAL, "newton_max_iter must be in [1, 64]");
     if (std::isnan(o->chi2_cut)) return fail(P2R_EINVAL, "chi2_cut is NaN");
     if (o->fp64_fallback < 0 || o->fp64_fallback > 3) return fail(P2R_EINVAL, "fp64_fallback must be 0, 1, 2 or 3");
+    if (o->cyl_start < 0 || o->cyl_start > 1) return fail(P2R_EINVAL, "cyl_start must be 0 or 1");
     return P2R_OK;
 }
 
@@ -210,6 +212,7 @@ void p2r_opts_default(p2r_opts* o) {
     o->mlp = nullptr;
     o->use_graph = 1;
     o->helix_evals = nullptr;
+    o->cyl_start = 0;
 }
 
 int p2r_ctx_create(p2r_ctx** out, int device, const char* tune_cache_path) {
@@ -464,7 +467,21 @@ void p2r_mlp_destroy(p2r_mlp* m) {
     if (!m) return;
     DeviceGuard g(m->device);
     if (m->block) (void)hipFree(m->block);
+    if (m->d.part) (void)hipFree(m->d.part);
     delete m;
+}
+
+// per-workgroup gradient rows for a batch of B (grown on demand)
+static int mlp_reserve(p2r_mlp* m, int32_t B) {
+    const int nb = p2r::mlp_grad_blocks(B);
+    if (nb <= m->d.part_blocks) return P2R_OK;
+    if (m->d.part) (void)hipFree(m->d.part);
+    m->d.part = nullptr;
+    m->d.part_blocks = 0;
+    hipError_t e = hipMalloc(&m->d.part, (size_t)nb * (p2r::MLP_NPARAM + 1) * sizeof(float));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    m->d.part_blocks = nb;
+    return P2R_OK;
 }
 
 int p2r_mlp_set_params(p2r_mlp* m, const float* host_params) {
@@ -523,6 +540,8 @@ int p2r_mlp_grads(p2r_mlp* m, const float* x, const float* t, int32_t B, float* 
     if (B <= 0) return fail(P2R_EINVAL, "batch must be positive");
     if (!x || !t) return fail(P2R_EINVAL, "NULL buffer");
     DeviceGuard g(m->device);
+    rc = mlp_reserve(m, B);
+    if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = p2r::mlp_grads(m->d, x, t, B, s);
     if (e == hipSuccess && grads_out)

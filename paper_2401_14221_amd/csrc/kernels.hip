@@ -80,8 +80,14 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
                 const float w = -st.q * KAPPA * P.bz * st.p[3];
                 float feat[MLP_IN], sl;
                 const bool ok = mlp_features_of(st.p[0], st.p[1], cphi, sphi, w, R, feat, sl);
-                const float yv = mlp_infer(*Wl, feat);            // whole wave
-                if (ok && !bad && finite3(m)) s_start = sl * (1.0f + yv * (1.0f / MLP_TARGET_SCALE));
+                // an offset the compiler cannot see through keeps the weight
+                // reads in LDS inside the loop; hoisted, they would pin ~130
+                // registers for the whole fit
+                int zoff = 0;
+                asm volatile("" : "+s"(zoff));
+                const MlpWeights* Wv = reinterpret_cast<const MlpWeights*>(reinterpret_cast<const char*>(Wl) + zoff);
+                const float yv = mlp_infer(*Wv, feat);            // whole wave
+                if (ok && !bad && finite3(m)) s_start = sl * (1.0f + sinhf(fminf(fmaxf(yv, -8.0f), 8.0f)) * (1.0f / MLP_TARGET_SCALE));
             }
             if (!bad) {
                 float c2 = 0.0f;

@@ -30,7 +30,7 @@ constexpr int OFF_B2 = OFF_W2 + MLP_H * MLP_H;
 constexpr int OFF_W3 = OFF_B2 + MLP_H;
 constexpr int OFF_B3 = OFF_W3 + MLP_H;
 
-constexpr float MLP_TARGET_SCALE = 100.0f;   // the network predicts 100 (s / s_line - 1)
+constexpr float MLP_TARGET_SCALE = 100.0f;   // the network predicts asinh(100 (s / s_line - 1))
 constexpr float MLP_ACCEPT_CM = 1e-3f;        // proposals with |r(s0) - R| above this are rejected
 constexpr float KAPPA_MLP = 2.99792458e-3f;  // GeV / (T cm)
 
@@ -59,8 +59,12 @@ struct MlpDev {
     float* grad;     // [MLP_NPARAM] gradient accumulator
     float* loss;     // [1]
     MlpWeights* w;   // BF16 / FP32 copies the kernels use
+    float* part;     // [part_blocks][MLP_NPARAM + 1] per-workgroup partial gradients
+    int32_t part_blocks;
     int32_t step;
 };
+
+int mlp_grad_blocks(int32_t B);
 
 hipError_t mlp_recast(const MlpDev& d, hipStream_t s);
 hipError_t mlp_forward(const MlpDev& d, const float* x, float* y, int32_t B, hipStream_t s);

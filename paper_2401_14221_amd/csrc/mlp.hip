@@ -69,9 +69,14 @@ struct GradTiles {
     float dy[64];
 };
 
+// Each workgroup writes its partial gradient (and loss) to its own row of
+// `part` ([blocks][MLP_NPARAM + 1]); mlp_reduce_kernel sums the rows in a
+// fixed order, so gradients are reproducible bit for bit.
 __global__ void __launch_bounds__(64) mlp_grads_kernel(const MlpWeights* __restrict__ Wg, const float* __restrict__ x,
                                                        const float* __restrict__ t, int32_t B,
-                                                       float* __restrict__ grad, float* __restrict__ loss) {
+                                                       float* __restrict__ part) {
+    float* grad = part + (size_t)blockIdx.x * (MLP_NPARAM + 1);
+    float* loss = grad + MLP_NPARAM;
     __shared__ MlpWeights W;
     __shared__ GradTiles T;
     load_weights_lds(W, Wg);
@@ -90,7 +95,7 @@ __global__ void __launch_bounds__(64) mlp_grads_kernel(const MlpWeights* __restr
     float sq = d * d / (float)B;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
-    if (l == 0) atomicAdd(loss, sq);
+    if (l == 0) *loss = sq;
     // dy of the samples of column blocks 0 and 1
     const float dy_other = __shfl_xor(dy, 32);
     const float dyb[2] = {hi ? dy_other : dy, hi ? dy : dy_other};
@@ -157,11 +162,11 @@ __global__ void __launch_bounds__(64) mlp_grads_kernel(const MlpWeights* __restr
         // ill-defined at w3 = 0, so it is accumulated from h2 directly below
     }
 #pragma unroll
-    for (int h = 0; h < MLP_H; ++h) atomicAdd(&grad[OFF_W2 + o * MLP_H + h], gw2[h]);
+    for (int h = 0; h < MLP_H; ++h) grad[OFF_W2 + o * MLP_H + h] = gw2[h];
 #pragma unroll
-    for (int k = 0; k < MLP_IN; ++k) atomicAdd(&grad[OFF_W1 + o * MLP_IN + k], gw1[k]);
-    atomicAdd(&grad[OFF_B2 + o], gb2);
-    atomicAdd(&grad[OFF_B1 + o], gb1);
+    for (int k = 0; k < MLP_IN; ++k) grad[OFF_W1 + o * MLP_IN + k] = gw1[k];
+    grad[OFF_B2 + o] = gb2;
+    grad[OFF_B1 + o] = gb1;
     // w3 and b3: sum over the samples of dy * h2 (each lane has 32 hidden units of 2 samples)
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
@@ -173,19 +178,23 @@ __global__ void __launch_bounds__(64) mlp_grads_kernel(const MlpWeights* __restr
             // reduce over the 32 lanes of this half (same hidden unit)
 #pragma unroll
             for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            if (r32 == 0) atomicAdd(&grad[OFF_W3 + mb * 32 + blk_row(j, hi)], v);
+            if (r32 == 0) grad[OFF_W3 + mb * 32 + blk_row(j, hi)] = v;
         }
     gb3 = dy;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) gb3 += __shfl_xor(gb3, off);
-    if (l == 0) atomicAdd(&grad[OFF_B3], gb3);
+    if (l == 0) grad[OFF_B3] = gb3;
     (void)gw3;
 }
 
-__global__ void mlp_zero_kernel(float* __restrict__ g, int n, float* __restrict__ loss) {
+__global__ void mlp_reduce_kernel(const float* __restrict__ part, int nblk, float* __restrict__ g,
+                                  float* __restrict__ loss) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) g[i] = 0.0f;
-    if (i == 0) *loss = 0.0f;
+    if (i > MLP_NPARAM) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (MLP_NPARAM + 1) + i];
+    if (i < MLP_NPARAM) g[i] = s;
+    else *loss = s;
 }
 
 __global__ void mlp_adam_kernel(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v,
@@ -215,7 +224,7 @@ __global__ void mlp_features_kernel(int32_t n, const float* __restrict__ par, co
 #pragma unroll
     for (int k = 0; k < MLP_IN; ++k) x[(size_t)i * MLP_IN + k] = f[k];
     if (s_line) s_line[i] = sl;
-    if (t && s_label) t[i] = sl > 0.0f ? MLP_TARGET_SCALE * (s_label[i] / sl - 1.0f) : 0.0f;
+    if (t && s_label) t[i] = sl > 0.0f ? asinhf(MLP_TARGET_SCALE * (s_label[i] / sl - 1.0f)) : 0.0f;
 }
 
 hipError_t mlp_recast(const MlpDev& d, hipStream_t s) {
@@ -229,10 +238,13 @@ hipError_t mlp_forward(const MlpDev& d, const float* x, float* y, int32_t B, hip
     return hipGetLastError();
 }
 
+int mlp_grad_blocks(int32_t B) { return (B + 63) / 64; }
+
 hipError_t mlp_grads(const MlpDev& d, const float* x, const float* t, int32_t B, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_zero_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, d.grad, MLP_NPARAM, d.loss);
-    if (B <= 0) return hipGetLastError();
-    hipLaunchKernelGGL(mlp_grads_kernel, dim3((B + 63) / 64), dim3(64), 0, s, d.w, x, t, B, d.grad, d.loss);
+    const int nblk = mlp_grad_blocks(B);
+    hipLaunchKernelGGL(mlp_grads_kernel, dim3(nblk), dim3(64), 0, s, d.w, x, t, B, d.part);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, s, d.part, nblk, d.grad,
+                       d.loss);
     return hipGetLastError();
 }
 

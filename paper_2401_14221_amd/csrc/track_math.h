@@ -40,6 +40,13 @@ constexpr int NUSED_SHIFT = 8;
 constexpr float PD_TAU32 = 1e-3f;
 constexpr double PD_TAU64 = 1e-6;
 
+// Correctly rounded reciprocal and quotient.  A bare v_rcp_f32 (1 ulp)
+// saves the division sequence, but the extra rounding moves the propagated
+// position by a few ulp, which at r ~ 100 cm is a visible fraction of a
+// 100 um hit's residual; the fit keeps the IEEE result.
+__device__ __forceinline__ float frcp(float b) { return 1.0f / b; }
+__device__ __forceinline__ float fdiv(float a, float b) { return a / b; }
+
 // packed index of (i, j), j <= i
 constexpr int I21(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
@@ -49,6 +56,7 @@ struct Params {
     int32_t max_iter;
     float chi2_cut;
     int32_t fp64_fallback;
+    int32_t start_mode;   // cylinder start: 0 straight line (plain), 1 closed form
 };
 
 struct State {
@@ -81,7 +89,7 @@ __device__ __forceinline__ void sinc_terms(float u, float& su, float& cu, float&
         su = u * S;
     } else {
         sincosf(u, &su, &cu);
-        float iu = 1.0f / u;
+        float iu = frcp(u);
         S = su * iu;
         dS = (cu - S) * iu;
     }
@@ -134,9 +142,9 @@ __device__ __forceinline__ float line_path(float x, float y, float cphi, float s
     float lo, hi;   // lo <= hi
     if (b >= 0.0f) {
         lo = -(b + sq);
-        hi = (b + sq) > 0.0f ? dr2 / (b + sq) : 0.0f;
+        hi = (b + sq) > 0.0f ? fdiv(dr2, b + sq) : 0.0f;
     } else {
-        lo = dr2 / (b - sq);
+        lo = fdiv(dr2, b - sq);
         hi = sq - b;
     }
     *ok = disc >= 0.0f && hi > -BACK_TOL;
@@ -157,7 +165,7 @@ __device__ __forceinline__ float atan_ratio(float t) {   // atan(t) / t
         float t2 = t * t;
         return 1.0f + t2 * (-1.0f / 3.0f + t2 * (1.0f / 5.0f + t2 * (-1.0f / 7.0f + t2 * (1.0f / 9.0f))));
     }
-    return atanf(t) / t;
+    return fdiv(atanf(t), t);
 }
 
 __device__ __forceinline__ bool closed_form_cylinder(float x, float y, float cphi, float sphi, float w, float R,
@@ -177,9 +185,9 @@ __device__ __forceinline__ bool closed_form_cylinder(float x, float y, float cph
         float s;
         if (den[k] == 0.0f) {
             if (w == 0.0f) continue;             // line root at infinity
-            s = PI_F / fabsf(w);                 // t = +-inf: exactly half a turn
+            s = fdiv(PI_F, fabsf(w));            // t = +-inf: exactly half a turn
         } else {
-            float c = d / den[k];
+            float c = fdiv(d, den[k]);
             float t = 0.5f * w * c;
             s = c * atan_ratio(t);
         }
@@ -196,8 +204,8 @@ __device__ __forceinline__ bool closed_form_cylinder(float x, float y, float cph
 __device__ __forceinline__ bool newton_cylinder(float x, float y, float cphi, float sphi, float w, float R,
                                                 float tol, int max_iter, float s0, float& s, HelixPt& h,
                                                 int& iters, bool have_first = false) {
-    const float inv2R = 0.5f / R;
-    const float invR = 1.0f / R;
+    const float invR = frcp(R);
+    const float inv2R = 0.5f * invR;
     s = s0;
     for (int it = 0; it < max_iter; ++it) {
         if (!(have_first && it == 0)) helix_at(x, y, cphi, sphi, w, s, h);
@@ -205,7 +213,7 @@ __device__ __forceinline__ bool newton_cylinder(float x, float y, float cphi, fl
         iters = it + 1;
         if (fabsf(f) <= tol) return true;
         float fp = (h.x * h.cp + h.y * h.sp) * invR;
-        s -= f / fp;
+        s -= fdiv(f, fp);
     }
     return false;
 }
@@ -233,7 +241,7 @@ __device__ __forceinline__ void jacobian_cylinder(float x, float y, float w, flo
     float hs2 = 0.5f * s * s;
     float dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
     float dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
-    float iD = 1.0f / (h.x * h.cp + h.y * h.sp);
+    float iD = frcp(h.x * h.cp + h.y * h.sp);
     float dsx = -h.x * iD;
     float dsy = -h.y * iD;
     float dsphi = -(h.x * y - x * h.y) * iD;
@@ -265,7 +273,7 @@ __device__ __forceinline__ void jacobian_cylinder(float x, float y, float w, flo
     J.z[2] = 1.0f;
     J.z[3] = cot * dsipt;
     J.z[4] = cot * dsphi;
-    J.z[5] = -s / (sinth * sinth);
+    J.z[5] = -fdiv(s, sinth * sinth);
 }
 
 // Plane: g = z' - Z; ds/dz = -tan(theta), ds/dtheta = s / (sin cos), others 0.
@@ -276,7 +284,7 @@ __device__ __forceinline__ void jacobian_plane(float w, float kq, float s, float
     float dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
     float dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
     float dsz = -tanth;
-    float dsth = s / (sinth * costh);
+    float dsth = fdiv(s, sinth * costh);
     J.a[0][0] = 1.0f;  J.a[0][1] = 0.0f;  J.a[0][2] = h.cp * dsz;  J.a[0][3] = kq * dxw;
     J.a[0][4] = -h.chord * h.sm;  J.a[0][5] = h.cp * dsth;
     J.a[1][0] = 0.0f;  J.a[1][1] = 1.0f;  J.a[1][2] = h.sp * dsz;  J.a[1][3] = kq * dyw;
@@ -359,6 +367,7 @@ __device__ __forceinline__ void transport(const Jac& J, float* c) {
 // 3x3 symmetric inverse by cofactors, with the positive-definiteness test
 // on the leading minors (equivalent to Cholesky pivots d_k > tau S_kk):
 //   S00 > 0,  m2 = S00 S11 - S10^2 > tau S00 S11,  det > tau S22 m2.
+
 template <typename T>
 __device__ __forceinline__ bool inv3_spd(const T s[6], T inv[6], T tau) {
     // s: packed (00, 10, 11, 20, 21, 22)
@@ -383,8 +392,16 @@ __device__ __forceinline__ bool inv3_spd(const T s[6], T inv[6], T tau) {
 // an FP64 inverse keeps; so this path also forms the gain and the Joseph
 // covariance in FP64.  Kept out of line, with loops over small arrays, so its
 // registers do not weigh on the FP32 path that runs almost always.
-__device__ __noinline__ uint32_t kalman_update_fp64(float* p, float* c, const float* m, const float* V,
-                                                    float chi2_cut, float* chi2) {
+struct Fp64Io {
+    float p[6], c[21], m[3], V[6], chi2;
+};
+
+__device__ __noinline__ uint32_t kalman_update_fp64(Fp64Io* io, float chi2_cut) {
+    float* p = io->p;
+    float* c = io->c;
+    const float* m = io->m;
+    const float* V = io->V;
+    float* chi2 = &io->chi2;
     double C[6][6], Vd[3][3], S[6], Si[6], K[6][3], A[6][6], M[6][6];
 #pragma unroll 1
     for (int i = 0; i < 6; ++i)
@@ -469,7 +486,27 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
     if (P.fp64_fallback == 2 || !inv3_spd<float>(S, Si, PD_TAU32)) {
         if (!P.fp64_fallback) return ST_S_NOT_PD;
         flags |= ST_FP64_FALLBACK;
-        if (P.fp64_fallback != 1) return kalman_update_fp64(st.p, st.c, m, V, P.chi2_cut, &chi2);
+        if (P.fp64_fallback != 1) {
+            // the out-of-line call works on a copy made here, so that the
+            // state itself never has its address taken and stays in registers
+            Fp64Io io;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) io.p[k] = st.p[k];
+#pragma unroll
+            for (int k = 0; k < 21; ++k) io.c[k] = st.c[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) io.m[k] = m[k];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) io.V[k] = V[k];
+            io.chi2 = chi2;
+            const uint32_t r = kalman_update_fp64(&io, P.chi2_cut);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) st.p[k] = io.p[k];
+#pragma unroll
+            for (int k = 0; k < 21; ++k) st.c[k] = io.c[k];
+            chi2 = io.chi2;
+            return r;
+        }
         double Sd[6], Sid[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) Sd[k] = (double)c[k] + (double)V[k];
@@ -585,14 +622,14 @@ __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float
     int pre = 0;
     if (!isnan(s_start)) {
         helix_at(x, y, cphi, sphi, w, s_start, h);
-        const float f0 = (fmaf(h.x, h.x, h.y * h.y) - R * R) * (0.5f / R);
+        const float f0 = (fmaf(h.x, h.x, h.y * h.y) - R * R) * (0.5f * frcp(R));
         have_first = fabsf(f0) <= accept_cm && s_start > -BACK_TOL;
         if (!have_first) {
             o.flags |= ST_ML_REJECTED;
             pre = 1;
         }
     }
-    if (!have_first) {
+    if (!have_first && !(P.start_mode == 1 && closed_form_cylinder(x, y, cphi, sphi, w, R, s0))) {
         s0 = line_path(x, y, cphi, sphi, R, &line_ok);
         if (!line_ok && !closed_form_cylinder(x, y, cphi, sphi, w, R, s0)) { o.flags |= ST_NO_CROSSING; return o; }
     }
@@ -608,7 +645,7 @@ __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float
     }
     float sinth, costh;
     sincosf(st.p[5], &sinth, &costh);
-    float cot = costh / sinth;
+    float cot = fdiv(costh, sinth);
     Jac J;
     jacobian_cylinder(x, y, w, kq, s, cot, sinth, h, J);
     st.p[0] = h.x;
@@ -630,7 +667,7 @@ __device__ __forceinline__ StepOut step_plane(State& st, float Z, const float m[
     if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
     float sinth, costh;
     sincosf(st.p[5], &sinth, &costh);
-    float tanth = sinth / costh;
+    float tanth = fdiv(sinth, costh);
     float s = (Z - st.p[2]) * tanth;     // ahead (or at most BACK_TOL behind), within half a turn
     float kq = -st.q * KAPPA * P.bz;
     float w = kq * st.p[3];

@@ -52,7 +52,7 @@ def make_training_set(mlp, n_tracks: int, seed: int, device="cuda"):
     return x[keep].contiguous(), t[keep].contiguous(), dict(par=par[keep], q=q[keep], R=R[keep], s=s[keep], sl=sl[keep])
 
 
-def train(ctx, n_tracks=500_000, epochs=12, batch=8192, lr=2e-3, seed=None, init=None, log=print,
+def train(ctx, n_tracks=500_000, epochs=30, batch=8192, lr=2e-3, seed=None, init=None, log=print,
           stream=None, max_seconds=None):
     """Train a fresh network; returns (mlp, history)."""
     import torch
@@ -96,7 +96,7 @@ def proposal_quality(mlp, n_tracks=20_000, seed=2024):
     import torch
     x, t, d = make_training_set(mlp, n_tracks, seed)
     y = mlp.forward(x)
-    s0 = d["sl"] * (1.0 + y / 100.0)
+    s0 = d["sl"] * (1.0 + torch.sinh(y.clamp(-8, 8)) / 100.0)
     e_mlp = (s0 - d["s"]).abs()
     e_line = (d["sl"] - d["s"]).abs()
     return dict(median_err_mlp=float(e_mlp.median()), median_err_line=float(e_line.median()),
@@ -108,7 +108,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_CKPT)
     ap.add_argument("--tracks", type=int, default=500_000)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=2e-3)
     a = ap.parse_args()

@@ -5,11 +5,17 @@ Tolerances (FP32 GPU against FP64 oracle on the same FP32-rounded inputs):
               phi (compared modulo 2 pi), 0 for 1/pT and theta;
   chi2:       |d| <= 1e-3 max(ref, 1);
   covariance: element (i, j) passes when |d| <= 1e-3 |ref| or
-              |d| / sqrt(ref_ii ref_jj) <= 1e-5 (elements that vanish in
-              exact arithmetic, such as those along the surface normal, are
-              judged relative to the diagonal scale; diagonals are floored at
-              1e-12 of the largest position variance, for rows that vanish
-              identically such as z after a plane);
+              |d| / sqrt(ref_ii ref_jj) <= 1e-4.  The second form is for
+              elements near zero (correlations that change sign, those along
+              the surface normal), whose relative error is unbounded: the
+              covariance is carried along the fitted state through
+              state-dependent Jacobians, so the 1e-4 relative state
+              difference allowed above moves every element by up to ~1e-4 of
+              sqrt(C_ii C_jj) (measured: up to a few 1e-5).  The position diagonals
+              are floored at 1e-4 of the track's largest position variance,
+              because along the last surface's normal -- z after a plane, x or
+              y when a cylinder's normal lies along an axis -- the variance
+              itself is rounding noise);
   status:     flags bit-exact except FP64_FALLBACK (GPU only); the count of
               applied updates exact.
 Tracks whose reachability of a surface differs between FP32 and FP64 (the
@@ -27,6 +33,7 @@ ST_FP64_FALLBACK = 1 << 2
 ST_NO_CROSSING = 1 << 0
 ST_NEWTON_FAIL = 1 << 1
 ST_CHI2_CUT = 1 << 7
+NORM_TOL = 1e-4      # covariance error in units of sqrt(C_ii C_jj)
 
 
 def compare(gpu: dict, ref: dict, max_excluded_frac: float = 1e-4, ctx: str = "") -> dict:
@@ -63,15 +70,17 @@ def compare(gpu: dict, ref: dict, max_excluded_frac: float = 1e-4, ctx: str = ""
     cnan = np.isnan(gc) & np.isnan(rc)
     dc[cnan] = 0.0
     diag = np.abs(rc[:, [0, 2, 5, 9, 14, 20]])
-    # a row that vanishes in exact arithmetic (z after a plane: z' = Z) has an
-    # oracle diagonal at rounding level; floor it at 1e-12 of the position block
-    diag = np.maximum(diag, 1e-12 * diag[:, :3].max(1, keepdims=True))
+    # the position block has an exact null direction (the normal of the last
+    # surface): z after a plane, or x / y when a cylinder's normal lies along an
+    # axis.  Its diagonal is rounding noise, so the position diagonals used for
+    # normalisation are floored at 1e-4 of the track's largest position variance
+    diag[:, :3] = np.maximum(diag[:, :3], 1e-4 * diag[:, :3].max(1, keepdims=True))
     scale = np.sqrt(diag[:, IL[0]] * diag[:, IL[1]])
     ok_rel = dc <= 1e-3 * np.abs(rc)
-    ok_norm = dc <= 1e-5 * scale
+    ok_norm = dc <= NORM_TOL * scale
     okc = ok_rel | ok_norm | cnan
     okc[~keep] = True
-    assert okc.all(), _worst(f"{ctx}: cov", dc, np.maximum(1e-3 * np.abs(rc), 1e-5 * scale), okc)
+    assert okc.all(), _worst(f"{ctx}: cov", dc, np.maximum(1e-3 * np.abs(rc), NORM_TOL * scale), okc)
     relp = np.abs(d) / np.maximum(np.abs(rp), np.maximum(PAR_F, 1e-30))
     normerr = np.where(keep[:, None], dc / np.maximum(scale, 1e-300), 0.0)
     return dict(n=n, excluded=n_excl, cov_norm_err_max=float(normerr.max()),

@@ -248,3 +248,17 @@ def test_autotune_picks_a_variant(ctx, tmp_path):
     assert c2.variant_name(0) == c.variant_name(0)
     c.autotune(1, 32768, 20)
     assert c.layout_width(1) == 64
+
+
+def test_closed_form_start_matches_oracle(ctx):
+    """The closed-form FP32 crossing as the Newton start: same results, ~1 helix evaluation per layer."""
+    d = ev.make_barrel_event(ev.P2R_THROUGHPUT.with_(seed=88), n_tracks=5000)
+    r = oracle.fit_event(d, "barrel")
+    counts = {}
+    for mode in (0, 1):
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        g = run_p2r(ctx, d, 64, cyl_start=mode, helix_evals=cnt.data_ptr())
+        compare(g, r, ctx=f"cyl_start={mode}")
+        counts[mode] = float(cnt.item()) / (5000 * 20)
+    print("helix evaluations per track-layer: line start %.3f, closed-form start %.3f" % (counts[0], counts[1]))
+    assert counts[1] < counts[0]
