@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="headline p2r figure only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--variant", default=None,
+                    help="time this p2r kernel variant (as reported in config.variant) without autotuning")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: a run that finds its workload there times the same variant "
+                         "without re-tuning (profiled runs use the variant the timed run chose)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -59,13 +64,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the p2r fit kernel from the committed counter profile, if current."""
+def measured_traffic(variant: str):
+    """HBM bytes per launch of the timed p2r kernel from the committed counter profile.
+
+    None unless the profile was taken from the same kernel sources and the
+    same variant (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by its
+    reading for a plain device copy of known size)."""
     p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "p2r_fit_traffic.json")
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("variant") != variant:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -103,11 +112,13 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    ctx = p2r.Context(0)
+    ctx = p2r.Context(0, tune_cache=args.tune_cache)
     cfg = ev.P2R_THROUGHPUT
     L = len(cfg.surfaces)
     n = cfg.n_total
-    if not args.no_autotune:
+    if args.variant:
+        ctx.set_variant(0, args.variant)
+    elif not args.no_autotune:
         with torch.cuda.stream(stream):
             ctx.autotune(0, n, L, stream=stream)
     W = ctx.layout_width(0)
@@ -143,7 +154,7 @@ def main():
                    "layers": L, "track_layers": tl, "width": W, "variant": ctx.variant_name(0),
                    "parallelism": "one lane per track, one GPU"},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "frac": tflops / FP32_PEAK_TFLOPS, "traffic": measured_traffic(ctx.variant_name(0)),
                      "kernel": ctx.variant_name(0), "flop_per_track_layer": P2R_FLOP_PER_TL},
         "hbm": {"achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
                 "bytes_per_launch": alg_bytes},
@@ -154,6 +165,17 @@ def main():
                 "wall_ms_per_step": wall_ms},
     }
     res["config"]["kernel_source_hash"] = kernel_source_hash()
+    if not args.no_extra:
+        # the same workload from the closed-form FP32 crossing as Newton's start
+        # (one helix evaluation per layer instead of two)
+        opts_cf = p2r._lib.default_opts(width=W, cyl_start=1)
+
+        def step_cf():
+            ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts_cf, stream=stream)
+
+        ms_cf, _ = timed(step_cf, args.steps, args.warmup, stream)
+        res["closed_form_start"] = {"ms_per_step": ms_cf, "value": tl / (ms_cf * 1e-3), "unit": UNIT}
+        log(f"p2r closed-form start: {ms_cf:.3f} ms/step")
     if args.calib_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

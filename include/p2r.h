@@ -165,6 +165,12 @@ int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, vo
 /* Description of the variant in use for `which` (host string owned by ctx). */
 const char* p2r_variant_name(p2r_ctx* ctx, int which);
 
+/* Use the plain variant named `name` (as p2r_variant_name reports it) for
+ * `which` (0 p2r, 1 p2z, 2 ragged) from now on, without timing anything:
+ * to reproduce a tuned choice, e.g. under a profiler.  P2R_ENOTUNED if no
+ * such variant is compiled; the context's choice is then unchanged. */
+int p2r_set_variant(p2r_ctx* ctx, int which, const char* name);
+
 /* ---------------------------------------------------------------------
  * Learned path-length proposal (not in the paper; the north-star
  * extension): an MLP 7 -> 64 -> 64 -> 1 with ReLU, BF16 weights on the

@@ -65,6 +65,7 @@ def library():
         for f in (L.p2r_propagate_update, L.p2z_propagate_update):
             f.argtypes = [vp, C.POINTER(Opts), i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.p2r_autotune.argtypes = [vp, C.c_int, i32, i32, vp]
+        L.p2r_set_variant.argtypes = [vp, C.c_int, C.c_char_p]
         L.fit_tracks_batched.argtypes = [vp, C.POINTER(Opts), i32, i64, i32] + [vp] * 13
         L.p2r_mlp_create.argtypes = [vp, C.POINTER(vp)]
         L.p2r_mlp_destroy.argtypes = [vp]
@@ -142,6 +143,9 @@ class Context:
 
     def variant_name(self, which: int = 0) -> str:
         return library().p2r_variant_name(self._h, which).decode()
+
+    def set_variant(self, which: int, name: str):
+        _check(library().p2r_set_variant(self._h, which, name.encode()))
 
     def autotune(self, which: int, n_tracks: int, n_layers: int, stream=None):
         _check(library().p2r_autotune(self._h, which, n_tracks, n_layers, _stream(stream)))

@@ -258,6 +258,16 @@ int p2r_layout_width(p2r_ctx* ctx, int which, int32_t* W_out) {
     return P2R_OK;
 }
 
+int p2r_set_variant(p2r_ctx* ctx, int which, const char* name) {
+    if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
+    if (which < 0 || which > 2) return fail(P2R_EINVAL, "which must be 0 (p2r), 1 (p2z) or 2 (ragged)");
+    if (!name) return fail(P2R_EINVAL, "name is NULL");
+    const p2r::Variant* v = find_variant(which, name);
+    if (!v || v->learned) return fail(P2R_ENOTUNED, "no plain kernel variant named '%s' for which=%d", name, which);
+    ctx->chosen[which] = (int)(v - p2r::variants().data());
+    return P2R_OK;
+}
+
 const char* p2r_variant_name(p2r_ctx* ctx, int which) {
     if (!ctx || which < 0 || which > 2) return "";
     const p2r::Variant* v = nullptr;

@@ -40,12 +40,56 @@ constexpr int NUSED_SHIFT = 8;
 constexpr float PD_TAU32 = 1e-3f;
 constexpr double PD_TAU64 = 1e-6;
 
-// Correctly rounded reciprocal and quotient.  A bare v_rcp_f32 (1 ulp)
-// saves the division sequence, but the extra rounding moves the propagated
-// position by a few ulp, which at r ~ 100 cm is a visible fraction of a
-// 100 um hit's residual; the fit keeps the IEEE result.
-__device__ __forceinline__ float frcp(float b) { return 1.0f / b; }
-__device__ __forceinline__ float fdiv(float a, float b) { return a / b; }
+// Reciprocal and quotient: v_rcp_f32 (1 ulp) followed by one Newton
+// correction of the result, r + r (1 - b r) and q + r (a - b q) with the
+// residuals formed exactly by FMA.  The result is within 1 ulp and almost
+// always the correctly rounded one, in 3-4 instructions instead of the ~17
+// of the IEEE sequence, whose extra steps only rescale operands near the
+// denormal and overflow ranges (the fit's operands are lengths, angles and
+// their ratios, far from both).  A bare v_rcp_f32 is not enough: its extra
+// rounding moves propagated positions by a few ulp, a visible fraction of
+// a 100 um hit's residual at r ~ 100 cm.
+__device__ __forceinline__ float frcp(float b) {
+    const float r = __builtin_amdgcn_rcpf(b);
+    return fmaf(fmaf(-b, r, 1.0f), r, r);
+}
+__device__ __forceinline__ float fdiv(float a, float b) {
+    const float r = __builtin_amdgcn_rcpf(b);
+    const float q = a * r;
+    return fmaf(fmaf(-b, q, a), r, q);
+}
+
+// Square root for starting values only (v_sqrt_f32, 1 ulp): the iteration
+// that follows removes its error.
+__device__ __forceinline__ float sqrt_start(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// sin and cos of x for |x| <= 1e4 (larger arguments take the library
+// routine): x = k pi/2 + r with pi/2 split in three FP32 parts (Cody and
+// Waite's reduction, each product subtracted by FMA), |r| <= pi/4, then the
+// Taylor series of sin r to r^9 and cos r to r^10 (truncation below 3e-9)
+// and the quadrant's swap and signs.  Within 1.5 ulp of the exact values.
+__device__ __forceinline__ void sincos_fit(float x, float* sn, float* cs) {
+    if (!(fabsf(x) <= 1.0e4f)) { sincosf(x, sn, cs); return; }
+    const float k = rintf(x * 0.636619746685028f);                 // 2/pi
+    float r = fmaf(k, -1.5707963705062866f, x);                     // pi/2 = C1 + C2 + C3
+    r = fmaf(k, 4.371138828673793e-08f, r);
+    r = fmaf(k, 1.7763568394002505e-15f, r);
+    const float r2 = r * r;
+    float ps = fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    ps = fmaf(r2, ps, 1.0f / 120.0f);
+    ps = fmaf(r2, ps, -1.0f / 6.0f);
+    const float sr = fmaf(r * r2, ps, r);
+    float pc = fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    pc = fmaf(r2, pc, -1.0f / 720.0f);
+    pc = fmaf(r2, pc, 1.0f / 24.0f);
+    pc = fmaf(r2, pc, -0.5f);
+    const float cr = fmaf(r2, pc, 1.0f);
+    const int q = (int)k;
+    const float a = (q & 1) ? cr : sr;      // sin: sr, cr, -sr, -cr for q = 0..3
+    const float b = (q & 1) ? sr : cr;      // cos: cr, -sr, -cr, sr
+    *sn = (q & 2) ? -a : a;
+    *cs = ((q + 1) & 2) ? -b : b;
+}
 
 // packed index of (i, j), j <= i
 constexpr int I21(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
@@ -88,7 +132,7 @@ __device__ __forceinline__ void sinc_terms(float u, float& su, float& cu, float&
         dS = u * (-1.0f / 3.0f + u2 * (1.0f / 30.0f + u2 * (-1.0f / 840.0f + u2 * (1.0f / 45360.0f))));
         su = u * S;
     } else {
-        sincosf(u, &su, &cu);
+        sincos_fit(u, &su, &cu);
         float iu = frcp(u);
         S = su * iu;
         dS = (cu - S) * iu;
@@ -138,7 +182,7 @@ __device__ __forceinline__ float line_path(float x, float y, float cphi, float s
     float r0sq = fmaf(x, x, y * y);
     float dr2 = R * R - r0sq;
     float disc = fmaf(b, b, dr2);
-    float sq = sqrtf(fmaxf(disc, 0.0f));
+    float sq = sqrt_start(fmaxf(disc, 0.0f));
     float lo, hi;   // lo <= hi
     if (b >= 0.0f) {
         lo = -(b + sq);
@@ -176,7 +220,7 @@ __device__ __forceinline__ bool closed_form_cylinder(float x, float y, float cph
     float alpha = 1.0f + a * w - 0.25f * w * w * d;
     float disc = fmaf(b, b, alpha * d);
     if (disc < 0.0f) return false;
-    float sq = sqrtf(disc);
+    float sq = sqrt_start(disc);
     float den[2] = {b + sq, b - sq};
     bool have = false;
     float best = 0.0f;
@@ -478,49 +522,68 @@ __device__ __noinline__ uint32_t kalman_update_fp64(Fp64Io* io, float chi2_cut) 
 // FP64 update for every surface (testing).
 // Returns 0, or ST_S_NOT_PD / ST_CHI2_CUT when the update is skipped;
 // ST_FP64_FALLBACK is OR-ed into *flags when an FP64 path ran.
+//
+// The FP32 arithmetic has no branch: a lane whose update is skipped (or was
+// done by the FP64 path) runs it with S^-1 and w set to zero, so that K = 0,
+// A = I and every FMA below returns its accumulator unchanged -- p and C
+// come out bit for bit as they went in.  Branching around it instead makes
+// the compiler copy the whole state into merge registers on every layer.
 __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], const float V[6],
                                                   const Params& P, float& chi2, uint32_t& flags) {
     float* c = st.c;
     float S[6] = {c[0] + V[0], c[1] + V[1], c[2] + V[2], c[3] + V[3], c[4] + V[4], c[5] + V[5]};
     float Si[6];
-    if (P.fp64_fallback == 2 || !inv3_spd<float>(S, Si, PD_TAU32)) {
-        if (!P.fp64_fallback) return ST_S_NOT_PD;
-        flags |= ST_FP64_FALLBACK;
-        if (P.fp64_fallback != 1) {
-            // the out-of-line call works on a copy made here, so that the
-            // state itself never has its address taken and stays in registers
-            Fp64Io io;
+    const bool pd32 = inv3_spd<float>(S, Si, PD_TAU32);
+    uint32_t res = 0;
+    bool done = false;                    // the state was updated by the FP64 path
+    if (P.fp64_fallback == 2 || !pd32) {
+        if (!P.fp64_fallback) {
+            res = ST_S_NOT_PD;
+        } else {
+            flags |= ST_FP64_FALLBACK;
+            if (P.fp64_fallback != 1) {
+                // the out-of-line call works on a copy made here, so that the
+                // state itself never has its address taken and stays in registers
+                Fp64Io io;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) io.p[k] = st.p[k];
+                for (int k = 0; k < 6; ++k) io.p[k] = st.p[k];
 #pragma unroll
-            for (int k = 0; k < 21; ++k) io.c[k] = st.c[k];
+                for (int k = 0; k < 21; ++k) io.c[k] = st.c[k];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) io.m[k] = m[k];
+                for (int k = 0; k < 3; ++k) io.m[k] = m[k];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) io.V[k] = V[k];
-            io.chi2 = chi2;
-            const uint32_t r = kalman_update_fp64(&io, P.chi2_cut);
+                for (int k = 0; k < 6; ++k) io.V[k] = V[k];
+                io.chi2 = chi2;
+                res = kalman_update_fp64(&io, P.chi2_cut);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) st.p[k] = io.p[k];
+                for (int k = 0; k < 6; ++k) st.p[k] = io.p[k];
 #pragma unroll
-            for (int k = 0; k < 21; ++k) st.c[k] = io.c[k];
-            chi2 = io.chi2;
-            return r;
+                for (int k = 0; k < 21; ++k) st.c[k] = io.c[k];
+                chi2 = io.chi2;
+                done = true;
+            } else {
+                double Sd[6], Sid[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) Sd[k] = (double)c[k] + (double)V[k];
+                if (!inv3_spd<double>(Sd, Sid, PD_TAU64)) res = ST_S_NOT_PD;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) Si[k] = (float)Sid[k];
+            }
         }
-        double Sd[6], Sid[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) Sd[k] = (double)c[k] + (double)V[k];
-        if (!inv3_spd<double>(Sd, Sid, PD_TAU64)) return ST_S_NOT_PD;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) Si[k] = (float)Sid[k];
     }
     float r0 = m[0] - st.p[0], r1 = m[1] - st.p[1], r2 = m[2] - st.p[2];
     float w0 = Si[0] * r0 + Si[1] * r1 + Si[3] * r2;
     float w1 = Si[1] * r0 + Si[2] * r1 + Si[4] * r2;
     float w2 = Si[3] * r0 + Si[4] * r1 + Si[5] * r2;
     float c2 = r0 * w0 + r1 * w1 + r2 * w2;
-    if (P.chi2_cut > 0.0f && c2 > P.chi2_cut) return ST_CHI2_CUT;
-    chi2 = c2;
+    if (res == 0 && !done && P.chi2_cut > 0.0f && c2 > P.chi2_cut) res = ST_CHI2_CUT;
+    const bool apply = res == 0 && !done;
+    if (apply) chi2 = c2;
+    w0 = apply ? w0 : 0.0f;
+    w1 = apply ? w1 : 0.0f;
+    w2 = apply ? w2 : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Si[k] = apply ? Si[k] : 0.0f;
     // K = P S^-1 with P = C' H^T (rows c(i,0..2)); KV = K V
     float K[6][3], KV[6][3];
 #pragma unroll
@@ -548,7 +611,7 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
 #pragma unroll
         for (int l = 0; l < 6; ++l)
             if (l <= i || l < 3) M[i][l] = Mv(i, l);
-    // C+ = M A^T + K V K^T (lower triangle)
+    // C+ = M A^T + K V K^T (lower triangle), one FMA chain per element
     float n[21];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
@@ -558,19 +621,24 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
             a = fmaf(-M[i][0], K[l][0], a);
             a = fmaf(-M[i][1], K[l][1], a);
             a = fmaf(-M[i][2], K[l][2], a);
-            float q = KV[i][0] * K[l][0];
-            q = fmaf(KV[i][1], K[l][1], q);
-            q = fmaf(KV[i][2], K[l][2], q);
-            n[I21(i, l)] = a + q;
+            a = fmaf(KV[i][0], K[l][0], a);
+            a = fmaf(KV[i][1], K[l][1], a);
+            a = fmaf(KV[i][2], K[l][2], a);
+            n[I21(i, l)] = a;
         }
 #pragma unroll
     for (int k = 0; k < 21; ++k) c[k] = n[k];
-    return 0;
+    return res;
 }
 
+// phi into (-pi, pi].  After a layer phi has moved by at most half a turn
+// plus the update's correction, so one conditional 2 pi step is enough; an
+// input far outside the range takes the general reduction first.
 __device__ __forceinline__ float wrap_phi(float a) {
-    float r = a - TWO_PI_F * floorf((a + PI_F) * INV_TWO_PI_F);
-    return r <= -PI_F ? r + TWO_PI_F : (r > PI_F ? r - TWO_PI_F : r);
+    float r = a;
+    if (!(fabsf(r) <= 3.0f * PI_F)) r = a - TWO_PI_F * floorf((a + PI_F) * INV_TWO_PI_F);
+    r = r > PI_F ? r - TWO_PI_F : r;
+    return r <= -PI_F ? r + TWO_PI_F : r;
 }
 
 __device__ __forceinline__ bool finite3(const float m[3]) {
@@ -605,7 +673,7 @@ __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float
     if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
     float x = st.p[0], y = st.p[1];
     float sphi, cphi;
-    sincosf(st.p[4], &sphi, &cphi);
+    sincos_fit(st.p[4], &sphi, &cphi);
     float kq = -st.q * KAPPA * P.bz;
     float w = kq * st.p[3];
     if (!cylinder_reachable(x, y, cphi, sphi, w, R)) { o.flags = ST_NO_CROSSING; return o; }
@@ -644,7 +712,7 @@ __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float
         if (!conv || !(s > -BACK_TOL) || fabsf(w * s) > PI_F) { o.flags |= ST_NEWTON_FAIL; return o; }
     }
     float sinth, costh;
-    sincosf(st.p[5], &sinth, &costh);
+    sincos_fit(st.p[5], &sinth, &costh);
     float cot = fdiv(costh, sinth);
     Jac J;
     jacobian_cylinder(x, y, w, kq, s, cot, sinth, h, J);
@@ -666,14 +734,14 @@ __device__ __forceinline__ StepOut step_plane(State& st, float Z, const float m[
     StepOut o{0u, false, 0};
     if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
     float sinth, costh;
-    sincosf(st.p[5], &sinth, &costh);
+    sincos_fit(st.p[5], &sinth, &costh);
     float tanth = fdiv(sinth, costh);
     float s = (Z - st.p[2]) * tanth;     // ahead (or at most BACK_TOL behind), within half a turn
     float kq = -st.q * KAPPA * P.bz;
     float w = kq * st.p[3];
     if (!(s > -BACK_TOL) || !(fabsf(w * s) <= PI_F)) { o.flags = ST_NO_CROSSING; return o; }
     float sphi, cphi;
-    sincosf(st.p[4], &sphi, &cphi);
+    sincos_fit(st.p[4], &sphi, &cphi);
     HelixPt h;
     helix_at(st.p[0], st.p[1], cphi, sphi, w, s, h);
     Jac J;

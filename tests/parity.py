@@ -18,6 +18,13 @@ Tolerances (FP32 GPU against FP64 oracle on the same FP32-rounded inputs):
               itself is rounding noise);
   status:     flags bit-exact except FP64_FALLBACK (GPU only); the count of
               applied updates exact.
+Covariance tolerances are multiplied by the conditioning of the final
+crossing, 1 / cos(incidence) for a track that ends on a cylinder (1 for a
+plane).  The path-length derivative ds*/dp = -(dg/dp) / (dg/ds) divides by
+dg/ds = cos(incidence), so FP32 rounding in the transport of a track that
+grazes its last cylinder is amplified by that factor; for almost every
+track it is close to 1 (the largest seen, 43, belongs to a 0.56 GeV track
+whose largest radius lies 0.1 mm outside its last layer).
 Tracks whose reachability of a surface differs between FP32 and FP64 (the
 surface grazes the track's largest radius), or whose hit chi2 falls on the
 other side of a chi2 cut, are listed and excluded from the value comparison;
@@ -36,8 +43,51 @@ ST_CHI2_CUT = 1 << 7
 NORM_TOL = 1e-4      # covariance error in units of sqrt(C_ii C_jj)
 
 
-def compare(gpu: dict, ref: dict, max_excluded_frac: float = 1e-4, ctx: str = "") -> dict:
-    """gpu/ref dicts with par (n,6), cov (n,21), chi2 (n,), status (n,) [ref: + nused]."""
+def incidence_condition(ref_par, final_surface) -> np.ndarray:
+    """Per-track factor 1 / cos(incidence) at the final surface (1 for planes).
+
+    final_surface: "cylinder", "plane", or a per-track array (0 cylinder,
+    1 plane).  cos(incidence) on a cylinder is the radial component of the
+    transverse direction, |x cos(phi) + y sin(phi)| / r, taken from the
+    oracle's final state."""
+    p = np.asarray(ref_par, np.float64)
+    n = p.shape[0]
+    if isinstance(final_surface, str):
+        cyl = np.full(n, final_surface == "cylinder")
+    else:
+        cyl = np.asarray(final_surface) == 0
+    r = np.hypot(p[:, 0], p[:, 1])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        c = np.abs(p[:, 0] * np.cos(p[:, 4]) + p[:, 1] * np.sin(p[:, 4])) / r
+    c = np.where(np.isfinite(c), c, 1.0)
+    return np.where(cyl, 1.0 / np.clip(c, 1e-3, 1.0), 1.0)
+
+
+def final_surface_of(par, offsets, surf_type, surf_val) -> np.ndarray:
+    """0/1 kind of the surface each (oracle) final state lies on, for ragged
+    fits: the last of the track's surfaces that the final position is on."""
+    p = np.asarray(par, np.float64)
+    n = p.shape[0]
+    out = np.zeros(n, np.int64)
+    r = np.hypot(p[:, 0], p[:, 1])
+    for t in range(n):
+        a, b = int(offsets[t]), int(offsets[t + 1])
+        best = None
+        for h in range(a, b):
+            d = abs(r[t] - surf_val[h]) if surf_type[h] == 0 else abs(p[t, 2] - surf_val[h])
+            if d < 1e-3:
+                best = h
+        if best is not None:
+            out[t] = int(surf_type[best])
+    return out
+
+
+def compare(gpu: dict, ref: dict, max_excluded_frac: float = 1e-4, ctx: str = "",
+            final_surface="cylinder") -> dict:
+    """gpu/ref dicts with par (n,6), cov (n,21), chi2 (n,), status (n,) [ref: + nused].
+
+    final_surface: "cylinder", "plane" or a per-track 0/1 array (see
+    incidence_condition)."""
     gp, rp = np.asarray(gpu["par"], np.float64), np.asarray(ref["par"], np.float64)
     gc, rc = np.asarray(gpu["cov"], np.float64), np.asarray(ref["cov"], np.float64)
     gx, rx = np.asarray(gpu["chi2"], np.float64), np.asarray(ref["chi2"], np.float64)
@@ -76,18 +126,20 @@ def compare(gpu: dict, ref: dict, max_excluded_frac: float = 1e-4, ctx: str = ""
     # normalisation are floored at 1e-4 of the track's largest position variance
     diag[:, :3] = np.maximum(diag[:, :3], 1e-4 * diag[:, :3].max(1, keepdims=True))
     scale = np.sqrt(diag[:, IL[0]] * diag[:, IL[1]])
-    ok_rel = dc <= 1e-3 * np.abs(rc)
-    ok_norm = dc <= NORM_TOL * scale
+    cond = incidence_condition(rp, final_surface)[:, None]
+    ok_rel = dc <= 1e-3 * np.abs(rc) * cond
+    ok_norm = dc <= NORM_TOL * scale * cond
     okc = ok_rel | ok_norm | cnan
     okc[~keep] = True
-    assert okc.all(), _worst(f"{ctx}: cov", dc, np.maximum(1e-3 * np.abs(rc), NORM_TOL * scale), okc)
+    assert okc.all(), _worst(f"{ctx}: cov", dc, np.maximum(1e-3 * np.abs(rc), NORM_TOL * scale) * cond, okc)
     relp = np.abs(d) / np.maximum(np.abs(rp), np.maximum(PAR_F, 1e-30))
     normerr = np.where(keep[:, None], dc / np.maximum(scale, 1e-300), 0.0)
     return dict(n=n, excluded=n_excl, cov_norm_err_max=float(normerr.max()),
                 cov_norm_err_p999=float(np.quantile(normerr, 0.999)), max_rel_par=relp[keep].max(0) if keep.any() else np.zeros(6),
                 max_rel_chi2=float((dx / np.maximum(rx, 1.0))[keep].max()) if keep.any() else 0.0,
                 cov_rel_pass=int(ok_rel[keep].sum()), cov_norm_only=int((ok_norm & ~ok_rel)[keep].sum()),
-                fp64_fallbacks=int(((gs & ST_FP64_FALLBACK) != 0).sum()))
+                fp64_fallbacks=int(((gs & ST_FP64_FALLBACK) != 0).sum()),
+                max_incidence_condition=float(cond.max()) if n else 1.0)
 
 
 def _worst(what, d, tol, ok):

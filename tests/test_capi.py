@@ -42,3 +42,9 @@ def test_null_context_other_calls():
     assert lib.p2r_autotune(None, 0, 10, 10, None) == p2r.P2R_EINVAL
     assert lib.p2r_ctx_create(None, 0, None) == p2r.P2R_EINVAL
     lib.p2r_ctx_destroy(None)          # no-op
+
+
+def test_set_variant_argument_errors():
+    lib = p2r.library()
+    assert lib.p2r_set_variant(None, 0, b"p2r_w64_e0_u1") == p2r.P2R_EINVAL
+    assert b"ctx" in lib.p2r_last_error()

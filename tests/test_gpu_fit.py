@@ -92,7 +92,7 @@ def test_p2z_parity(ctx):
     d = ev.make_disk_event(ev.P2Z_THROUGHPUT, n_tracks=3000)
     g = run_p2z(ctx, d)
     r = oracle.fit_event(d, "disk")
-    rep = compare(g, r, ctx="p2z")
+    rep = compare(g, r, ctx="p2z", final_surface="plane")
     print("p2z", rep, flush=True)
 
 
@@ -124,7 +124,7 @@ def test_p2z_full_size_sampled(ctx):
     rng = np.random.default_rng(1)
     idx = np.unique(np.concatenate([rng.choice(n, 6000, replace=False), np.arange(n - 64, n)]))
     r = oracle.fit_event(_sub(d, idx), "disk")
-    rep = compare({k: v[idx] for k, v in g.items()}, r, ctx="p2z full")
+    rep = compare({k: v[idx] for k, v in g.items()}, r, ctx="p2z full", final_surface="plane")
     print("p2z full sampled", rep, flush=True)
     assert np.all(g["status"] & p2r.ST_DONE)
 
@@ -160,7 +160,8 @@ def test_fp64_update_forced_matches(ctx):
     compare(g, r, ctx="forced fp64")
     assert np.all(g["status"] & p2r.ST_FP64_FALLBACK)
     dz = ev.make_disk_event(ev.P2Z_THROUGHPUT, n_tracks=512)
-    compare(run_p2z(ctx, dz, fp64_fallback=2), oracle.fit_event(dz, "disk"), ctx="forced fp64 p2z")
+    compare(run_p2z(ctx, dz, fp64_fallback=2), oracle.fit_event(dz, "disk"), ctx="forced fp64 p2z",
+            final_surface="plane")
 
 
 def test_fp64_fallback_triggers_on_ill_conditioned_S(ctx):
@@ -248,6 +249,16 @@ def test_autotune_picks_a_variant(ctx, tmp_path):
     assert c2.variant_name(0) == c.variant_name(0)
     c.autotune(1, 32768, 20)
     assert c.layout_width(1) == 64
+    # a named choice is taken as is; an unknown name leaves the choice alone
+    c3 = p2r.Context(0)
+    c3.set_variant(0, "p2r_w128_e4_u1")
+    assert c3.variant_name(0) == "p2r_w128_e4_u1" and c3.layout_width(0) == 128
+    with pytest.raises(p2r.P2RError):
+        c3.set_variant(0, "no_such_kernel")
+    with pytest.raises(p2r.P2RError):
+        c3.set_variant(0, "p2r_mlp_w64_e0_u1")     # learned kernels are chosen by opts.mlp
+    assert c3.variant_name(0) == "p2r_w128_e4_u1"
+    c3.close()
 
 
 def test_closed_form_start_matches_oracle(ctx):

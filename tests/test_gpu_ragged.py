@@ -7,7 +7,7 @@ import oracle
 import paper_2401_14221_amd as p2r
 from synth import events as ev
 
-from .parity import compare
+from .parity import compare, final_surface_of
 
 pytestmark = pytest.mark.gpu
 
@@ -48,10 +48,11 @@ def test_ragged_parity_small(ctx):
     u = upload(d)
     H = int(d["offsets"][-1])
     r = oracle.fit_ragged(d, chi2_cut=CUT)
+    fs = final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"])
     s = torch.cuda.Stream()
     for use_graph in (0, 1):
         g = run(ctx, u, H, stream=s, use_graph=use_graph)
-        rep = compare(g, r, ctx=f"ragged graph={use_graph}")
+        rep = compare(g, r, ctx=f"ragged graph={use_graph}", final_surface=fs)
         print("ragged", use_graph, rep, flush=True)
     L = np.diff(d["offsets"])
     assert np.all(((g["status"] >> 8) & 0xFF) <= L)
@@ -84,7 +85,9 @@ def test_ragged_new_arguments_recapture(ctx):
         d = ev.make_ragged_event(ev.RAGGED.with_(seed=seed), n_tracks=n)
         u = upload(d)
         g = run(ctx, u, int(d["offsets"][-1]), stream=s)
-        compare(g, oracle.fit_ragged(d, chi2_cut=CUT), ctx=f"recapture n={n}")
+        r = oracle.fit_ragged(d, chi2_cut=CUT)
+        compare(g, r, ctx=f"recapture n={n}",
+                final_surface=final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"]))
 
 
 def test_ragged_edge_cases(ctx):
@@ -103,7 +106,7 @@ def test_ragged_edge_cases(ctx):
     H = int(off[-1])
     g = run(ctx, u, H, lmax=25)
     r = oracle.fit_ragged(e, chi2_cut=CUT)
-    compare(g, r, ctx="ragged edge")
+    compare(g, r, ctx="ragged edge", final_surface=final_surface_of(r["par"], off, st, e["surf_val"]))
     assert (g["status"][5] >> 8) & 0xFF == 0 and g["status"][5] & p2r.ST_DONE
     assert g["status"][10] & p2r.ST_BAD_INPUT
     # a track longer than max_surfaces is rejected as a whole
@@ -137,5 +140,6 @@ def test_ragged_full_size_sampled(ctx):
     sub = dict(offsets=sub_off, surf_type=d["surf_type"][hsel], surf_val=d["surf_val"][hsel],
                hits=d["hits"][hsel], hitcov=d["hitcov"][hsel], par=d["par"][idx], cov=d["cov"][idx], q=d["q"][idx])
     r = oracle.fit_ragged(sub, chi2_cut=CUT)
-    rep = compare({k: v[idx] for k, v in g.items()}, r, ctx="ragged full")
+    rep = compare({k: v[idx] for k, v in g.items()}, r, ctx="ragged full",
+                  final_surface=final_surface_of(r["par"], sub_off, sub["surf_type"], sub["surf_val"]))
     print("ragged full sampled", rep, flush=True)
