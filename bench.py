@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: a run that finds its workload there times the same variant "
                          "without re-tuning (profiled runs use the variant the timed run chose)")
+    ap.add_argument("--only", choices=["p2z", "ragged", "learned"], default=None,
+                    help="run just this secondary leg and print its record (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -113,6 +115,10 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     ctx = p2r.Context(0, tune_cache=args.tune_cache)
+    if args.only:
+        leg = {"p2z": p2z_leg, "ragged": ragged_leg, "learned": learned_leg}[args.only]
+        print(json.dumps({"leg": args.only, "result": leg(ctx, args, stream, ev, p2r, dev)}))
+        return
     cfg = ev.P2R_THROUGHPUT
     L = len(cfg.surfaces)
     n = cfg.n_total
@@ -191,9 +197,15 @@ def main():
 
 
 def extra_legs(ctx, args, stream, ev, p2r, dev):
+    out = {"p2z": p2z_leg(ctx, args, stream, ev, p2r, dev),
+           "ragged": ragged_leg(ctx, args, stream, ev, p2r, dev)}
+    out["learned"] = learned_leg(ctx, args, stream, ev, p2r, dev)
+    return out
+
+
+def p2z_leg(ctx, args, stream, ev, p2r, dev):
+    """p2z, 100 x 8192 x 20 disks; also the rate with host->device and device->host copies included."""
     import torch
-    out = {}
-    # p2z, 100 x 8192 x 20 disks; also the rate with host->device and device->host copies included
     cfg = ev.P2Z_THROUGHPUT
     L = len(cfg.surfaces)
     n = cfg.n_total
@@ -228,15 +240,18 @@ def extra_legs(ctx, args, stream, ev, p2r, dev):
     ms_x, _ = timed(step_xfer, max(3, args.steps // 2), 1, stream)
     tl = n * L
     alg = n * TRACK_BYTES + tl * HIT_BYTES
-    out["p2z"] = {"workload": cfg.name, "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT,
-                  "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                  "tflops": tl * P2Z_FLOP_PER_TL / (ms * 1e-3) / 1e12,
-                  "with_transfers": {"ms_per_step": ms_x, "value": tl / (ms_x * 1e-3),
-                                     "note": "pinned host buffers, H2D + fit + D2H on one stream"}}
+    out = {"workload": cfg.name, "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT,
+           "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+           "tflops": tl * P2Z_FLOP_PER_TL / (ms * 1e-3) / 1e12,
+           "with_transfers": {"ms_per_step": ms_x, "value": tl / (ms_x * 1e-3),
+                              "note": "pinned host buffers, H2D + fit + D2H on one stream"}}
     log(f"p2z: {ms:.3f} ms/step; with transfers {ms_x:.3f} ms")
-    del trk, hits, o
+    return out
 
-    # ragged batched fit, 1,000,000 tracks with 5..25 mixed surfaces, one graph launch per step
+
+def ragged_leg(ctx, args, stream, ev, p2r, dev):
+    """Ragged batched fit, 1,000,000 tracks with 5..25 mixed surfaces, one graph launch per step."""
+    import torch
     cfg = ev.RAGGED
     log(f"generating {cfg.name}")
     d = ev.make_ragged_event(cfg)
@@ -259,12 +274,10 @@ def extra_legs(ctx, args, stream, ev, p2r, dev):
 
     ms_r, _ = timed(rstep, args.steps, args.warmup, stream)
     alg_r = n * (TRACK_BYTES + 8) + H * (HIT_BYTES + 5)
-    out["ragged"] = {"workload": cfg.name, "ms_per_step": ms_r, "value": H / (ms_r * 1e-3), "unit": UNIT,
-                     "track_layers": H, "hbm_frac": alg_r / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                     "variant": ctx.variant_name(2), "note": "one HIP graph per step: sort + persistent fit"}
+    out = {"workload": cfg.name, "ms_per_step": ms_r, "value": H / (ms_r * 1e-3), "unit": UNIT,
+           "track_layers": H, "hbm_frac": alg_r / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+           "variant": ctx.variant_name(2), "note": "one HIP graph per step: sort + persistent fit"}
     log(f"ragged: {ms_r:.3f} ms/step, {H / (ms_r * 1e-3):.3e} track-layers/s")
-    del off, stype, sval, hpos, hcov, par, cov, q, ro
-    out["learned"] = learned_leg(ctx, args, stream, ev, p2r, dev)
     return out
 
 

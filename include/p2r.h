@@ -143,12 +143,16 @@ int p2z_propagate_update(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, i
  *   cov_out [n][21], chi2_out [n], status [n].  A surf_type other than 0/1
  *   skips that surface and sets BAD_INPUT.
  * The tracks are counting-sorted on the device by (surface count, |eta|
- * bin) and fitted by one persistent kernel whose waves take blocks of 64
- * sorted tracks from an atomic counter; the five kernels run as one HIP
- * graph, captured on the first call for a given set of arguments and
- * replayed afterwards (opts->use_graph, non-NULL stream).  The sort
- * workspace lives in the context (allocated on first use, grown when
- * needed): calls on one context must not overlap. */
+ * bin); the hits of every block of 64 sorted tracks are packed into
+ * coalesced rows, and one persistent kernel whose waves take blocks from an
+ * atomic counter fits them.  The six kernels run as one HIP graph, captured
+ * on the first call for a given set of arguments and replayed afterwards
+ * (opts->use_graph, non-NULL stream).  The workspace (sort arrays, 16 B per
+ * track; packed hits, 44 B per surface plus a few rows per sort key) lives
+ * in the context, allocated on first use and grown when needed: calls on
+ * one context must not overlap.  The CSR ranges of valid tracks must not
+ * overlap; tracks whose packed rows would not fit because they do are
+ * reported BAD_INPUT. */
 int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits,
                        int32_t max_surfaces, const int64_t* offsets, const uint8_t* surf_type,
                        const float* surf_val, const float* hit_pos, const float* hit_cov,

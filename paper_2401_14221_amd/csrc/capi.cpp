@@ -77,10 +77,14 @@ struct p2r_ctx {
     std::map<std::string, std::string> cache;  // key -> variant name
     // ragged workspace (owned)
     int32_t* rag_hist = nullptr;
+    int32_t* rag_base = nullptr;
     int32_t* rag_work = nullptr;
     int32_t* rag_perm = nullptr;
     int32_t* rag_keys = nullptr;
+    int32_t* rag_blk_off = nullptr;
+    float* rag_packed = nullptr;
     int32_t rag_n_cap = 0, rag_nkeys_cap = 0;
+    int64_t rag_packed_cap = 0;
     int rag_blocks_per_cu[2] = {0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -242,7 +246,8 @@ void p2r_ctx_destroy(p2r_ctx* ctx) {
     DeviceGuard g(ctx->device);
     if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
-    void* bufs[] = {ctx->rag_hist, ctx->rag_work, ctx->rag_perm, ctx->rag_keys};
+    void* bufs[] = {ctx->rag_hist, ctx->rag_base, ctx->rag_work, ctx->rag_perm, ctx->rag_keys, ctx->rag_blk_off,
+                    ctx->rag_packed};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete ctx;
@@ -353,21 +358,37 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     hipError_t e;
     // workspace
     const int nkeys = p2r::ragged_nkeys(max_surfaces);
+    const int64_t packed_rows = p2r::ragged_packed_rows(n_hits, max_surfaces);
+    if (packed_rows > INT32_MAX) return fail(P2R_EINVAL, "n_hits %lld too large for one call", (long long)n_hits);
     if (n_tracks > ctx->rag_n_cap) {
-        if (ctx->rag_perm) (void)hipFree(ctx->rag_perm);
-        if (ctx->rag_keys) (void)hipFree(ctx->rag_keys);
-        ctx->rag_perm = ctx->rag_keys = nullptr;
+        for (int32_t** b : {&ctx->rag_perm, &ctx->rag_keys, &ctx->rag_blk_off}) {
+            if (*b) (void)hipFree(*b);
+            *b = nullptr;
+        }
         ctx->rag_n_cap = 0;
+        const size_t nb1 = (size_t)(n_tracks + p2r::RAG_W - 1) / p2r::RAG_W + 1;
         if ((e = hipMalloc(&ctx->rag_perm, sizeof(int32_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMalloc(&ctx->rag_keys, sizeof(int32_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&ctx->rag_blk_off, sizeof(int32_t) * nb1)) != hipSuccess) return hip_fail(e, "hipMalloc");
         ctx->rag_n_cap = n_tracks;
     }
     if (nkeys > ctx->rag_nkeys_cap) {
-        if (ctx->rag_hist) (void)hipFree(ctx->rag_hist);
-        ctx->rag_hist = nullptr;
+        for (int32_t** b : {&ctx->rag_hist, &ctx->rag_base}) {
+            if (*b) (void)hipFree(*b);
+            *b = nullptr;
+        }
         ctx->rag_nkeys_cap = 0;
         if ((e = hipMalloc(&ctx->rag_hist, sizeof(int32_t) * nkeys)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&ctx->rag_base, sizeof(int32_t) * nkeys)) != hipSuccess) return hip_fail(e, "hipMalloc");
         ctx->rag_nkeys_cap = nkeys;
+    }
+    if (packed_rows > ctx->rag_packed_cap) {
+        if (ctx->rag_packed) (void)hipFree(ctx->rag_packed);
+        ctx->rag_packed = nullptr;
+        ctx->rag_packed_cap = 0;
+        const size_t bytes = sizeof(float) * (size_t)packed_rows * p2r::RAG_FIELDS * p2r::RAG_W;
+        if ((e = hipMalloc(&ctx->rag_packed, bytes)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        ctx->rag_packed_cap = packed_rows;
     }
     if (!ctx->rag_work && (e = hipMalloc(&ctx->rag_work, sizeof(int32_t))) != hipSuccess)
         return hip_fail(e, "hipMalloc");
@@ -395,9 +416,13 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     a.chi2 = chi2_out;
     a.status = status;
     a.hist = ctx->rag_hist;
+    a.base = ctx->rag_base;
     a.work = ctx->rag_work;
     a.perm = ctx->rag_perm;
     a.keys = ctx->rag_keys;
+    a.blk_off = ctx->rag_blk_off;
+    a.packed = ctx->rag_packed;
+    a.packed_cap = ctx->rag_packed_cap;
     a.nkeys = nkeys;
     a.nb = (n_tracks + p2r::RAG_W - 1) / p2r::RAG_W;
     a.grid = std::min(a.nb, ctx->cu_count * ctx->rag_blocks_per_cu[slot]);

@@ -37,10 +37,13 @@ struct FitLaunch {
 
 hipError_t launch_fit(const Variant& v, const FitLaunch& a, const Params& P, hipStream_t s);
 
-// Ragged path: tracks sorted by (surface count descending, |cot theta| bin),
-// then one persistent kernel over blocks of 64 sorted tracks.
+// Ragged path: tracks counting-sorted by (surface count descending, |eta|
+// bin), their hits packed per block of RAG_W sorted tracks into
+// [layer][RAG_FIELDS][RAG_W] rows, then one persistent kernel over the blocks.
 constexpr int RAG_W = 64;
 constexpr int RAG_ETA_BINS = 8;
+constexpr int RAG_FIELDS = 11;      // surface type, surface value, hit (3), hit covariance (6)
+constexpr int RAG_TPB = 1024;       // tracks per workgroup in the sort kernels
 
 struct RaggedLaunch {
     int32_t n;                 // tracks
@@ -59,15 +62,23 @@ struct RaggedLaunch {
     float* chi2;
     uint32_t* status;
     // workspace (device, owned by the context)
-    int32_t* hist;             // [nkeys] key histogram, then bucket cursors
+    int32_t* hist;             // [nkeys] tracks per sort key
+    int32_t* base;             // [nkeys] first sorted position of each key, then scatter cursors
     int32_t* work;             // [1] work-queue counter
     int32_t* perm;             // [n] sorted position -> track index
     int32_t* keys;             // [n] sort key of every track
+    int32_t* blk_off;          // [nb + 1] first packed layer row of each block
+    float* packed;             // [packed_cap][RAG_FIELDS][RAG_W] hits of the sorted blocks
+    int64_t packed_cap;        // layer rows available in packed
     int32_t nkeys;
     int32_t nb;                // blocks of RAG_W sorted tracks
     int32_t grid;              // persistent grid (one wave per workgroup)
 };
 
+// Layer rows the packed hits of n tracks with n_hits surfaces in total can
+// need when the CSR ranges do not overlap (blocks that would not fit are
+// reported as BAD_INPUT by the fit).
+int64_t ragged_packed_rows(int64_t n_hits, int lmax);
 int ragged_nkeys(int lmax);
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s);
 

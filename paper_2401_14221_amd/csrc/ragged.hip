@@ -3,15 +3,25 @@
 //
 // Schedule (all on the caller's stream, captured once into a HIP graph):
 //   1. rag_reset   zero the key histogram and the work-queue counter
-//   2. rag_hist    sort key of every track -> histogram (wave-aggregated atomics)
-//   3. rag_scan    exclusive scan of the histogram (one workgroup)
-//   4. rag_scatter counting-sort scatter -> perm[sorted position] = track
-//   5. rag_fit     persistent kernel: each wave takes the next block of 64
-//                  sorted tracks from an atomic counter until none is left
+//   2. rag_hist    sort key of every track; per-workgroup histogram in LDS,
+//                  then one global atomic per (workgroup, key)
+//   3. rag_scan    (one workgroup) bucket starts, and for every block of
+//                  RAG_W sorted tracks its first packed layer row
+//   4. rag_scatter counting-sort scatter -> perm[sorted position] = track,
+//                  ranks from LDS atomics, one cursor atomic per (workgroup, key)
+//   5. rag_pack    one workgroup per block: copies its tracks' hits from the
+//                  CSR arrays (coalesced reads of each track's run) through
+//                  an LDS tile into [layer][RAG_FIELDS][RAG_W] rows
+//   6. rag_fit     persistent kernel: each wave takes the next block from an
+//                  atomic counter, streams its packed rows (next layer
+//                  prefetched) and fits its 64 tracks
 // The key orders tracks by surface count (longest first, so the longest
 // blocks start first and the tail of the queue is short work) and then by a
 // |eta| bin, so the 64 lanes of a wave see similar surface sequences and
-// branch the same way between cylinders and planes.
+// branch the same way between cylinders and planes.  Gathering the hits
+// lane by lane (each lane walking its own track's run) evicts each lane's
+// cache lines before their next use, at 10-20x the algorithmic traffic; the
+// pack pass reads every run with consecutive lanes instead.
 #include "launch.h"
 #include "track_math.h"
 
@@ -19,28 +29,14 @@ namespace p2r {
 
 int ragged_nkeys(int lmax) { return (lmax + 1) * RAG_ETA_BINS + 1; }
 
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-// atomicAdd(&ctr[key], 1) for every lane with pred, aggregated per distinct
-// key within the wave; returns the lane's slot (old value + rank).
-__device__ __forceinline__ int aggregated_inc(int32_t* ctr, int key, bool pred) {
-    uint64_t todo = __ballot(pred);
-    const int lane = lane_id();
-    int ret = 0;
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int lkey = __shfl(key, leader);
-        const uint64_t grp = __ballot(pred && key == lkey) & todo;
-        int old = 0;
-        if (lane == leader) old = atomicAdd(&ctr[lkey], __popcll(grp));
-        old = __shfl(old, leader);
-        if ((grp >> lane) & 1ull) ret = old + __popcll(grp & ((1ull << lane) - 1ull));
-        todo &= ~grp;
-    }
-    return ret;
+int64_t ragged_packed_rows(int64_t n_hits, int lmax) {
+    // sum over blocks of the block's (largest) surface count: a block inside
+    // one key bucket holds RAG_W tracks of equal count; the last block and
+    // each block that straddles a bucket boundary add at most lmax
+    return (n_hits + RAG_W - 1) / RAG_W + (int64_t)lmax * ragged_nkeys(lmax) + 1;
 }
 
-__device__ __forceinline__ int track_key(const RaggedLaunch& a, int t) {
+__device__ __forceinline__ int track_key(const RaggedLaunch& a, int64_t t) {
     const int64_t h0 = a.offsets[t];
     const int64_t L = a.offsets[t + 1] - h0;
     const int invalid = a.nkeys - 1;
@@ -53,54 +49,201 @@ __device__ __forceinline__ int track_key(const RaggedLaunch& a, int t) {
     return (a.lmax - (int)L) * RAG_ETA_BINS + bin;
 }
 
+// surface count of the tracks of sort key k (0 for the invalid bucket)
+__device__ __forceinline__ int key_layers(const RaggedLaunch& a, int k) {
+    return k >= a.nkeys - 1 ? 0 : a.lmax - k / RAG_ETA_BINS;
+}
+
 __global__ void rag_reset(RaggedLaunch a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < a.nkeys) a.hist[i] = 0;
     if (i == 0) a.work[0] = 0;
 }
 
-__global__ void rag_hist(RaggedLaunch a) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = t < a.n;
-    const int key = ok ? track_key(a, t) : 0;
-    if (ok) a.keys[t] = key;
-    (void)aggregated_inc(a.hist, key, ok);
+// dynamic LDS: nkeys counters
+__global__ void __launch_bounds__(256) rag_hist(RaggedLaunch a) {
+    extern __shared__ int32_t lh[];
+    for (int k = threadIdx.x; k < a.nkeys; k += blockDim.x) lh[k] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * RAG_TPB;
+    for (int i = threadIdx.x; i < RAG_TPB; i += blockDim.x) {
+        const int64_t t = t0 + i;
+        if (t < a.n) {
+            const int key = track_key(a, t);
+            a.keys[t] = key;
+            atomicAdd(&lh[key], 1);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < a.nkeys; k += blockDim.x)
+        if (lh[k]) atomicAdd(&a.hist[k], lh[k]);
 }
 
-// exclusive scan of hist[0..nkeys) in place, one workgroup of 1024 threads
+// One workgroup of 1024 threads.  dynamic LDS: nkeys bucket starts.
+//   base[k]    = sum of hist[k'] for k' < k
+//   blk_off[b] = sum of Lb' for b' < b, Lb = surface count of the key bucket
+//                holding the block's first sorted position (its largest,
+//                since counts decrease along the sorted order); a block whose
+//                rows would pass packed_cap gets none (its tracks are then
+//                reported BAD_INPUT by the fit).
 __global__ void __launch_bounds__(1024) rag_scan(RaggedLaunch a) {
     __shared__ int32_t part[1024];
+    extern __shared__ int32_t sbase[];
     const int tid = threadIdx.x;
-    const int per = (a.nkeys + 1023) / 1024;
-    const int lo = tid * per;
-    const int hi = min(lo + per, a.nkeys);
-    int32_t s = 0;
-    for (int i = lo; i < hi; ++i) s += a.hist[i];
-    part[tid] = s;
+    {
+        const int per = (a.nkeys + 1023) / 1024;
+        const int lo = min(tid * per, a.nkeys), hi = min(lo + per, a.nkeys);
+        int32_t s = 0;
+        for (int i = lo; i < hi; ++i) s += a.hist[i];
+        part[tid] = s;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int32_t v = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += v;
+            __syncthreads();
+        }
+        int32_t run = tid > 0 ? part[tid - 1] : 0;
+        for (int i = lo; i < hi; ++i) {
+            const int32_t c = a.hist[i];
+            a.base[i] = run;
+            sbase[i] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    // rows of block b: the bucket of position 64 b is the largest k with
+    // sbase[k] <= 64 b (an empty bucket shares its start with the next one)
+    auto rows_of = [&](int b) -> int {
+        const int32_t pos = b * RAG_W;
+        int lo = 0, hi = a.nkeys - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sbase[mid] <= pos) lo = mid; else hi = mid - 1;
+        }
+        return key_layers(a, lo);
+    };
+    const int per = (a.nb + 1023) / 1024;
+    const int lo = min(tid * per, a.nb), hi = min(lo + per, a.nb);
+    int64_t s = 0;
+    for (int b = lo; b < hi; ++b) s += rows_of(b);
+    __syncthreads();
+    __shared__ int64_t part64[1024];
+    part64[tid] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = tid >= off ? part[tid - off] : 0;
+        const int64_t v = tid >= off ? part64[tid - off] : 0;
         __syncthreads();
-        part[tid] += v;
+        part64[tid] += v;
         __syncthreads();
     }
-    int32_t run = tid > 0 ? part[tid - 1] : 0;
-    for (int i = lo; i < hi; ++i) {
-        int32_t c = a.hist[i];
-        a.hist[i] = run;
-        run += c;
+    int64_t run = tid > 0 ? part64[tid - 1] : 0;
+    const int64_t cap = a.packed_cap;
+    for (int b = lo; b < hi; ++b) {
+        const int r = rows_of(b);
+        const int64_t start = run < cap ? run : cap;
+        a.blk_off[b] = (int32_t)start;
+        run += r;
+    }
+    if (tid == 1023) a.blk_off[a.nb] = (int32_t)(run < cap ? run : cap);
+}
+
+// dynamic LDS: 2 nkeys ints (ranks, workgroup bases)
+__global__ void __launch_bounds__(256) rag_scatter(RaggedLaunch a) {
+    extern __shared__ int32_t sh[];
+    int32_t* lh = sh;
+    int32_t* off = sh + a.nkeys;
+    for (int k = threadIdx.x; k < a.nkeys; k += blockDim.x) lh[k] = 0;
+    __syncthreads();
+    constexpr int PER = RAG_TPB / 256;
+    int key[PER], rank[PER];
+    const int64_t t0 = (int64_t)blockIdx.x * RAG_TPB;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int64_t t = t0 + threadIdx.x + j * 256;
+        key[j] = -1;
+        if (t < a.n) {
+            key[j] = a.keys[t];
+            rank[j] = atomicAdd(&lh[key[j]], 1);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < a.nkeys; k += blockDim.x)
+        if (lh[k]) off[k] = atomicAdd(&a.base[k], lh[k]);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int64_t t = t0 + threadIdx.x + j * 256;
+        if (key[j] >= 0) a.perm[off[key[j]] + rank[j]] = (int32_t)t;
     }
 }
 
-__global__ void rag_scatter(RaggedLaunch a) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = t < a.n;
-    const int key = ok ? a.keys[t] : 0;
-    const int pos = aggregated_inc(a.hist, key, ok);
-    if (ok) a.perm[pos] = t;
+// One workgroup of 256 threads per block of RAG_W sorted tracks.  Row j of
+// the block holds, for field f and the track at sorted position 64 b + l,
+// packed[((blk_off[b] + j) RAG_FIELDS + f) RAG_W + l].  The rows are built in
+// LDS tiles of up to PACK_ROWS rows for PACK_TRACKS tracks: for each track,
+// one wave reads the track's contiguous run from each CSR array with
+// consecutive lanes on consecutive elements (whole runs, so every fetched
+// cache line is used), and scatters the values into the tile's columns; the
+// tile then goes out as 64-byte pieces of the block's rows, which the L2
+// merges into whole lines.  Tile entries of a track with fewer rows keep
+// stale values, which the fit never reads (it stops at the track's count).
+constexpr int PACK_ROWS = 24;
+constexpr int PACK_TRACKS = 16;
+
+__global__ void __launch_bounds__(256) rag_pack(RaggedLaunch a) {
+    __shared__ float tile[PACK_ROWS * RAG_FIELDS * PACK_TRACKS];
+    __shared__ int32_t s_rows[RAG_W];
+    __shared__ int64_t s_h0[RAG_W];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t o = a.blk_off[b];
+    const int rows = a.blk_off[b + 1] - (int32_t)o;
+    if (tid < RAG_W) {
+        const int64_t p = (int64_t)b * RAG_W + tid;
+        int L = 0;
+        int64_t h0 = 0;
+        if (p < a.n) {
+            const int t = a.perm[p];
+            L = min(key_layers(a, a.keys[t]), rows);   // 0 for an invalid CSR range
+            if (L > 0) h0 = a.offsets[t];
+        }
+        s_rows[tid] = L;
+        s_h0[tid] = h0;
+    }
+    __syncthreads();
+    float* dst = a.packed + (size_t)o * (RAG_FIELDS * RAG_W);
+    for (int c0 = 0; c0 < rows; c0 += PACK_ROWS) {
+        const int nr = min(PACK_ROWS, rows - c0);
+        for (int k0 = 0; k0 < RAG_W; k0 += PACK_TRACKS) {
+#pragma unroll
+            for (int i = 0; i < PACK_TRACKS / 4; ++i) {
+                const int kt = wave + 4 * i;                   // track within the tile
+                const int m = min(nr, s_rows[k0 + kt] - c0);   // its rows in this tile
+                if (m <= 0) continue;
+                const int64_t h = s_h0[k0 + kt] + c0;
+                for (int e = lane; e < 6 * m; e += 64)
+                    tile[((e / 6) * RAG_FIELDS + 5 + e % 6) * PACK_TRACKS + kt] = a.hcov[h * 6 + e];
+                for (int e = lane; e < 3 * m; e += 64)
+                    tile[((e / 3) * RAG_FIELDS + 2 + e % 3) * PACK_TRACKS + kt] = a.hpos[h * 3 + e];
+                if (lane < m) {
+                    tile[(lane * RAG_FIELDS + 1) * PACK_TRACKS + kt] = a.sval[h + lane];
+                    tile[(lane * RAG_FIELDS) * PACK_TRACKS + kt] = (float)a.stype[h + lane];
+                }
+            }
+            __syncthreads();
+            float* d = dst + (size_t)c0 * (RAG_FIELDS * RAG_W) + k0;
+            for (int e = tid; e < nr * RAG_FIELDS * PACK_TRACKS; e += 256)
+                d[(size_t)(e / PACK_TRACKS) * RAG_W + e % PACK_TRACKS] = tile[e];
+            __syncthreads();
+        }
+    }
 }
 
-__device__ __forceinline__ void fit_ragged_track(const RaggedLaunch& a, const Params& P, int t) {
+__device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Params& P, int b, int lane) {
+    const int64_t p = (int64_t)b * RAG_W + lane;
+    if (p >= a.n) return;
+    const int t = a.perm[p];
     State st;
 #pragma unroll
     for (int f = 0; f < 6; ++f) st.p[f] = a.par_in[(size_t)t * 6 + f];
@@ -110,31 +253,41 @@ __device__ __forceinline__ void fit_ragged_track(const RaggedLaunch& a, const Pa
     st.q = (float)qi;
     const int64_t h0 = a.offsets[t];
     const int64_t L = a.offsets[t + 1] - h0;
+    const int64_t o = a.blk_off[b];
+    const int rows = a.blk_off[b + 1] - (int32_t)o;
     uint32_t flags = 0;
     int nused = 0;
     float chi2 = 0.0f;
-    if (L < 0 || L > a.lmax || h0 < 0 || h0 + L > a.n_hits || (qi != 1 && qi != -1) || bad_input(st)) {
+    if (L < 0 || L > a.lmax || h0 < 0 || h0 + L > a.n_hits || L > rows || (qi != 1 && qi != -1) ||
+        bad_input(st)) {
         flags = ST_BAD_INPUT;
     } else {
-        for (int j = 0; j < (int)L; ++j) {
-            const int64_t h = h0 + j;
-            const int type = a.stype[h];
-            const float v = a.sval[h];
-            const float m[3] = {a.hpos[h * 3], a.hpos[h * 3 + 1], a.hpos[h * 3 + 2]};
-            float V[6];
+        const float* src = a.packed + (size_t)o * (RAG_FIELDS * RAG_W) + lane;
+        float hb[RAG_FIELDS];
+        if (L > 0) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) V[k] = a.hcov[h * 6 + k];
-            float c2 = 0.0f;
-            StepOut o;
-            if (type == 0) {
-                o = step_cylinder(st, v, m, V, P, c2, newton_tol(P.tol, v), NAN);
-            } else if (type == 1) {
-                o = step_plane(st, v, m, V, P, c2);
-            } else {
-                o = StepOut{ST_BAD_INPUT, false, 0};
+            for (int f = 0; f < RAG_FIELDS; ++f) hb[f] = src[f * RAG_W];
+        }
+        for (int j = 0; j < (int)L; ++j) {
+            const float type = hb[0], v = hb[1];
+            const float m[3] = {hb[2], hb[3], hb[4]};
+            const float V[6] = {hb[5], hb[6], hb[7], hb[8], hb[9], hb[10]};
+            if (j + 1 < (int)L) {
+                const float* nx = src + (size_t)(j + 1) * (RAG_FIELDS * RAG_W);
+#pragma unroll
+                for (int f = 0; f < RAG_FIELDS; ++f) hb[f] = nx[f * RAG_W];
             }
-            flags |= o.flags;
-            if (o.updated) { ++nused; chi2 += c2; }
+            float c2 = 0.0f;
+            StepOut out;
+            if (type == 0.0f) {
+                out = step_cylinder(st, v, m, V, P, c2, newton_tol(P.tol, v), NAN);
+            } else if (type == 1.0f) {
+                out = step_plane(st, v, m, V, P, c2);
+            } else {
+                out = StepOut{ST_BAD_INPUT, false, 0};
+            }
+            flags |= out.flags;
+            if (out.updated) { ++nused; chi2 += c2; }
         }
     }
 #pragma unroll
@@ -156,8 +309,7 @@ rag_fit(RaggedLaunch a, Params P) {
         if (lane == 0) b = atomicAdd(a.work, 1);
         b = __shfl(b, 0);
         if (b >= a.nb) break;
-        const int k = b * RAG_W + lane;
-        if (k < a.n) fit_ragged_track(a, P, a.perm[k]);
+        fit_sorted_track(a, P, b, lane);
     }
 }
 
@@ -172,12 +324,14 @@ hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& 
     RaggedLaunch aa = a;
     Params pp = P;
     const int tb = 256;
+    const size_t lds_keys = sizeof(int32_t) * (size_t)a.nkeys;
     hipLaunchKernelGGL(rag_reset, dim3((a.nkeys + tb - 1) / tb), dim3(tb), 0, s, aa);
-    const int nbt = (a.n + tb - 1) / tb;
-    if (nbt > 0) {
-        hipLaunchKernelGGL(rag_hist, dim3(nbt), dim3(tb), 0, s, aa);
-        hipLaunchKernelGGL(rag_scan, dim3(1), dim3(1024), 0, s, aa);
-        hipLaunchKernelGGL(rag_scatter, dim3(nbt), dim3(tb), 0, s, aa);
+    const int64_t nwg = ((int64_t)a.n + RAG_TPB - 1) / RAG_TPB;
+    if (nwg > 0) {
+        hipLaunchKernelGGL(rag_hist, dim3((unsigned)nwg), dim3(tb), lds_keys, s, aa);
+        hipLaunchKernelGGL(rag_scan, dim3(1), dim3(1024), lds_keys, s, aa);
+        hipLaunchKernelGGL(rag_scatter, dim3((unsigned)nwg), dim3(tb), 2 * lds_keys, s, aa);
+        hipLaunchKernelGGL(rag_pack, dim3(a.nb), dim3(256), 0, s, aa);
         void* args[] = {&aa, &pp};
         hipError_t e = hipLaunchKernel(v.fn, dim3(a.grid), dim3(RAG_W), args, 0, s);
         if (e != hipSuccess) return e;
