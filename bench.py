@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: a run that finds its workload there times the same variant "
                          "without re-tuning (profiled runs use the variant the timed run chose)")
+    ap.add_argument("--sweep-variants", action="store_true",
+                    help="run every compiled p2r variant twice on the workload (for per-variant counters)")
     ap.add_argument("--only", choices=["p2z", "ragged", "learned"], default=None,
                     help="run just this secondary leg and print its record (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -69,16 +71,18 @@ def kernel_source_hash() -> str:
 def measured_traffic(variant: str):
     """HBM bytes per launch of the timed p2r kernel from the committed counter profile.
 
-    None unless the profile was taken from the same kernel sources and the
-    same variant (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by its
-    reading for a plain device copy of known size)."""
+    None unless the profile was taken from the same kernel sources; the
+    record holds every compiled variant (FETCH_SIZE and WRITE_SIZE per
+    dispatch, each scaled by its reading for a plain device copy of known
+    size)."""
     p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "p2r_fit_traffic.json")
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
-    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("variant") != variant:
+    if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    v = rec.get("variants", {}).get(variant)
+    return None if v is None else v.get("hbm_bytes_per_launch")
 
 
 def log(*a):
@@ -115,6 +119,13 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     ctx = p2r.Context(0, tune_cache=args.tune_cache)
+    if args.calib_copy:
+        # one plain device copy of 1 GiB: the counters' reading for known bytes
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.only:
         leg = {"p2z": p2z_leg, "ragged": ragged_leg, "learned": learned_leg}[args.only]
         print(json.dumps({"leg": args.only, "result": leg(ctx, args, stream, ev, p2r, dev)}))
@@ -142,6 +153,26 @@ def main():
 
     def step():
         ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts, stream=stream)
+
+    if args.sweep_variants:
+        rec = {}
+        for name in p2r.variant_names(0):
+            ctx.set_variant(0, name)
+            Wv = ctx.layout_width(0)
+            tv = p2r.pack_tracks(d["par"], d["cov"], d["q"], Wv, device=dev)
+            hv = p2r.pack_hits_p2r(d["hits"], d["hitcov"], Wv, device=dev)
+            ov = (torch.empty_like(tv), out[1], out[2])
+            o_v = p2r._lib.default_opts(width=Wv)
+            torch.cuda.synchronize()          # the packing ran on the current stream
+
+            def step_v():
+                ctx.p2r_propagate_update(n, radii, tv, hv, out=ov, opts=o_v, stream=stream)
+
+            rec[name] = timed(step_v, 2, 1, stream)[0]
+            del tv, hv, ov
+            log(f"sweep {name}: {rec[name]:.3f} ms")
+        print(json.dumps({"sweep": rec, "kernel_source_hash": kernel_source_hash()}))
+        return
 
     ms, wall_ms = timed(step, args.steps, args.warmup, stream)
     tl = n * L
@@ -182,12 +213,6 @@ def main():
         ms_cf, _ = timed(step_cf, args.steps, args.warmup, stream)
         res["closed_form_start"] = {"ms_per_step": ms_cf, "value": tl / (ms_cf * 1e-3), "unit": UNIT}
         log(f"p2r closed-form start: {ms_cf:.3f} ms/step")
-    if args.calib_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     del trk, hits, out
     if not args.no_extra:
         res["extra"] = extra_legs(ctx, args, stream, ev, p2r, dev)
@@ -298,6 +323,7 @@ def learned_leg(ctx, args, stream, ev, p2r, dev):
     trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device=dev)
     hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device=dev)
     radii = torch.as_tensor(d["surf"], dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()                  # the packing ran on the current stream
     res = {"workload": cfg.name}
     outs = {}
     for name, m in (("plain", None), ("learned", mlp)):
@@ -335,25 +361,26 @@ def learned_leg(ctx, args, stream, ev, p2r, dev):
 
 
 def cpu_baseline(d, ev):
-    """FP64 oracle on a bounded sample of the same workload, all host cores."""
+    """FP64 oracle on the same workload, all host cores (at most 16 threads).
+
+    The whole 960,000-track workload is fitted: about 1.2 s per run on 16
+    threads (~20 s of CPU-thread work), one warm-up and three timed runs."""
     import oracle
     ncores = len(os.sched_getaffinity(0))
     nthreads = min(ncores, 16)
-    n = 96_000
-    sub = {k: d[k][:n] for k in ("par", "cov", "q", "hits", "hitcov")}
-    sub["surf"] = d["surf"]
-    oracle.fit_event(sub, "barrel", nthreads=nthreads)          # warm-up
+    n = d["par"].shape[0]
+    oracle.fit_event(d, "barrel", nthreads=nthreads)          # warm-up
     times = []
     for _ in range(3):
         t = time.perf_counter()
-        oracle.fit_event(sub, "barrel", nthreads=nthreads)
+        oracle.fit_event(d, "barrel", nthreads=nthreads)
         times.append(time.perf_counter() - t)
-    tl = n * sub["hits"].shape[1]
+    tl = n * d["hits"].shape[1]
     v = tl / float(np.mean(times))
-    log(f"cpu oracle: {v:.3e} track-layers/s on {nthreads} threads")
+    log(f"cpu oracle: {v:.3e} track-layers/s on {nthreads} threads ({np.mean(times):.2f} s per run)")
     return {"value": v, "unit": UNIT, "cores": nthreads, "kind": "oracle",
-            "sample": f"first {n} of {d['par'].shape[0]} tracks x {sub['hits'].shape[1]} layers, "
-                      f"FP64 oracle (dual-number Jacobian, full 6x6 algebra), mean of 3 runs after 1 warm-up"}
+            "sample": f"the whole workload, {n} tracks x {d['hits'].shape[1]} layers, FP64 oracle "
+                      f"(dual-number Jacobian, full 6x6 algebra), mean of 3 runs after 1 warm-up"}
 
 
 if __name__ == "__main__":

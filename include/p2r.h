@@ -161,8 +161,9 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
 
 /* Autotune `which` (0 p2r, 1 p2z) on synthetic tracks of this shape: times
  * every compiled variant (width, waves per SIMD, layer-loop unroll) with HIP
- * events, keeps the fastest in the context and writes the cache file if the
- * context has one.  Allocates and frees temporary device buffers;
+ * events, keeps the fastest in the context (the default variant unless the
+ * fastest beats it by 3% or more) and writes the cache file if the context
+ * has one.  Allocates and frees temporary device buffers;
  * synchronises the stream. */
 int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, void* stream);
 
@@ -174,6 +175,10 @@ const char* p2r_variant_name(p2r_ctx* ctx, int which);
  * to reproduce a tuned choice, e.g. under a profiler.  P2R_ENOTUNED if no
  * such variant is compiled; the context's choice is then unchanged. */
 int p2r_set_variant(p2r_ctx* ctx, int which, const char* name);
+
+/* Name of the i-th compiled plain variant for `which` (0 p2r, 1 p2z,
+ * 2 ragged), i = 0, 1, ...; NULL past the last.  Static string. */
+const char* p2r_variant_at(int which, int i);
 
 /* ---------------------------------------------------------------------
  * Learned path-length proposal (not in the paper; the north-star

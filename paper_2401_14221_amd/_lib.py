@@ -66,6 +66,8 @@ def library():
             f.argtypes = [vp, C.POINTER(Opts), i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.p2r_autotune.argtypes = [vp, C.c_int, i32, i32, vp]
         L.p2r_set_variant.argtypes = [vp, C.c_int, C.c_char_p]
+        L.p2r_variant_at.argtypes = [C.c_int, C.c_int]
+        L.p2r_variant_at.restype = C.c_char_p
         L.fit_tracks_batched.argtypes = [vp, C.POINTER(Opts), i32, i64, i32] + [vp] * 13
         L.p2r_mlp_create.argtypes = [vp, C.POINTER(vp)]
         L.p2r_mlp_destroy.argtypes = [vp]
@@ -88,6 +90,17 @@ def exported_symbols():
     txt = open(_HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\(", txt, flags=re.M)) - {"defined"})
+
+
+def variant_names(which: int) -> list:
+    """Names of the compiled plain variants for which (0 p2r, 1 p2z, 2 ragged)."""
+    out, i = [], 0
+    while True:
+        nm = library().p2r_variant_at(which, i)
+        if nm is None:
+            return out
+        out.append(nm.decode())
+        i += 1
 
 
 def _check(rc):

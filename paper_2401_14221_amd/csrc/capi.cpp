@@ -263,6 +263,13 @@ int p2r_layout_width(p2r_ctx* ctx, int which, int32_t* W_out) {
     return P2R_OK;
 }
 
+const char* p2r_variant_at(int which, int i) {
+    int k = 0;
+    for (const auto& v : p2r::variants())
+        if (v.which == which && !v.learned && k++ == i) return v.name;
+    return nullptr;
+}
+
 int p2r_set_variant(p2r_ctx* ctx, int which, const char* name) {
     if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
     if (which < 0 || which > 2) return fail(P2R_EINVAL, "which must be 0 (p2r), 1 (p2z) or 2 (ragged)");
@@ -681,7 +688,7 @@ int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, vo
     p2r_opts o;
     p2r_opts_default(&o);
     p2r::Params P = params_of(&o);
-    float best = 1e30f;
+    float best = 1e30f, def_ms = -1.f;
     int best_i = -1;
     int cur_w = -1;
     for (size_t i = 0; i < vs.size(); ++i) {
@@ -700,12 +707,16 @@ int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, vo
         float ms = 0.f;
         TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
         if (ms < best) { best = ms; best_i = (int)i; }
+        if ((int)i == default_variant(which)) def_ms = ms;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     cleanup();
 #undef TRY
     if (best_i < 0) return fail(P2R_ENOTUNED, "no variant for which=%d", which);
+    // keep the default unless another variant is clearly faster: variants
+    // within a few percent trade places from run to run
+    if (def_ms > 0.f && best >= 0.97f * def_ms) best_i = default_variant(which);
     ctx->chosen[which] = best_i;
     ctx->cache[key] = vs[best_i].name;
     save_cache(ctx);

@@ -48,3 +48,10 @@ def test_set_variant_argument_errors():
     lib = p2r.library()
     assert lib.p2r_set_variant(None, 0, b"p2r_w64_e0_u1") == p2r.P2R_EINVAL
     assert b"ctx" in lib.p2r_last_error()
+
+
+def test_variant_listing_is_host_only():
+    names = p2r.variant_names(0)
+    assert "p2r_w64_e0_u1" in names and all(n.startswith("p2r_w") for n in names)
+    assert p2r.variant_names(1) and all(n.startswith("p2z_") for n in p2r.variant_names(1))
+    assert p2r.variant_names(2) and p2r.variant_names(7) == []
