@@ -611,19 +611,25 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
 #pragma unroll
         for (int l = 0; l < 6; ++l)
             if (l <= i || l < 3) M[i][l] = Mv(i, l);
-    // C+ = M A^T + K V K^T (lower triangle), one FMA chain per element
+    // C+ = M A^T + K V K^T = M + (K V - M H^T) K^T (lower triangle).  At
+    // the optimal gain M H^T = K V exactly, so D = K V - M H^T holds only
+    // the rounding residual that the Joseph form exists to absorb; forming
+    // it first subtracts the two nearly equal terms exactly (Sterbenz)
+    // instead of carrying both through each element's sum.
+    float D[6][3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) D[i][j] = KV[i][j] - M[i][j];
     float n[21];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
         for (int l = 0; l <= i; ++l) {
             float a = M[i][l];
-            a = fmaf(-M[i][0], K[l][0], a);
-            a = fmaf(-M[i][1], K[l][1], a);
-            a = fmaf(-M[i][2], K[l][2], a);
-            a = fmaf(KV[i][0], K[l][0], a);
-            a = fmaf(KV[i][1], K[l][1], a);
-            a = fmaf(KV[i][2], K[l][2], a);
+            a = fmaf(D[i][0], K[l][0], a);
+            a = fmaf(D[i][1], K[l][1], a);
+            a = fmaf(D[i][2], K[l][2], a);
             n[I21(i, l)] = a;
         }
 #pragma unroll
