@@ -213,6 +213,16 @@ def main():
         ms_cf, _ = timed(step_cf, args.steps, args.warmup, stream)
         res["closed_form_start"] = {"ms_per_step": ms_cf, "value": tl / (ms_cf * 1e-3), "unit": UNIT}
         log(f"p2r closed-form start: {ms_cf:.3f} ms/step")
+        # every step in FP64 (same inputs, results rounded to FP32)
+        opts_64 = p2r._lib.default_opts(width=W, fp64=1)
+
+        def step_64():
+            ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts_64, stream=stream)
+
+        ms_64, _ = timed(step_64, max(3, args.steps // 2), 1, stream)
+        res["fp64"] = {"ms_per_step": ms_64, "value": tl / (ms_64 * 1e-3), "unit": UNIT,
+                       "note": "every step in FP64 on the same FP32 inputs; results rounded to FP32"}
+        log(f"p2r FP64: {ms_64:.3f} ms/step")
     del trk, hits, out
     if not args.no_extra:
         res["extra"] = extra_legs(ctx, args, stream, ev, p2r, dev)
@@ -249,6 +259,12 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
         ctx.p2z_propagate_update(n, zs, trk, hits, out=o, opts=opts, stream=stream)
 
     ms, _ = timed(step, args.steps, args.warmup, stream)
+    opts_64 = p2r._lib.default_opts(fp64=1)
+
+    def step_64():
+        ctx.p2z_propagate_update(n, zs, trk, hits, out=o, opts=opts_64, stream=stream)
+
+    ms_64, _ = timed(step_64, max(3, args.steps // 2), 1, stream)
     out_h = torch.empty_like(trk_h).pin_memory()
     c2_h = torch.empty(n, dtype=torch.float32).pin_memory()
     st_h = torch.empty(n, dtype=torch.int32).pin_memory()
@@ -269,8 +285,9 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
            "tflops": tl * P2Z_FLOP_PER_TL / (ms * 1e-3) / 1e12,
            "with_transfers": {"ms_per_step": ms_x, "value": tl / (ms_x * 1e-3),
-                              "note": "pinned host buffers, H2D + fit + D2H on one stream"}}
-    log(f"p2z: {ms:.3f} ms/step; with transfers {ms_x:.3f} ms")
+                              "note": "pinned host buffers, H2D + fit + D2H on one stream"},
+           "fp64": {"ms_per_step": ms_64, "value": tl / (ms_64 * 1e-3)}}
+    log(f"p2z: {ms:.3f} ms/step; FP64 {ms_64:.3f} ms; with transfers {ms_x:.3f} ms")
     return out
 
 

@@ -73,7 +73,7 @@ typedef struct p2r_ctx p2r_ctx; /* opaque: device, tuned variants, workspace, gr
 
 /* Fit options.  p2r_opts_default() fills: bz 3.8 T, newton_tol 1e-6 cm,
  * 8 iterations, chi2 cut off, FP64 fallback 3, width 0 (tuned/default),
- * no MLP, graphs on, straight-line start. */
+ * no MLP, graphs on, straight-line start, FP32 arithmetic. */
 typedef struct {
     float bz_tesla;          /* field along +z */
     float newton_tol_cm;     /* |r(s) - R| tolerance, raised to 2 ulp(R) */
@@ -92,6 +92,10 @@ typedef struct {
     int32_t cyl_start;       /* start of the helix-to-cylinder Newton iteration without an MLP:
                                 0 = straight-line path (plain), 1 = closed-form FP32 crossing
                                 (t = tan(omega s / 2) quadratic), which Newton then only checks */
+    int32_t fp64;            /* 0 = FP32 arithmetic (default); 1 = every step in FP64 on the same
+                                FP32 inputs, results rounded to FP32 (a precision reference; the
+                                Newton tolerance becomes 1e-3 newton_tol_cm, the PD test the
+                                FP64 one; not with an MLP) */
 } p2r_opts;
 
 void p2r_opts_default(p2r_opts* o);

@@ -85,7 +85,7 @@ struct p2r_ctx {
     float* rag_packed = nullptr;
     int32_t rag_n_cap = 0, rag_nkeys_cap = 0;
     int64_t rag_packed_cap = 0;
-    int rag_blocks_per_cu[2] = {0, 0};
+    int rag_blocks_per_cu[3] = {0, 0, 0};   // FP32 fit, FP32 fit at 4 waves, FP64 fit
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     RaggedKey key;
@@ -109,14 +109,21 @@ const p2r::Variant* find_variant(int which, const std::string& name) {
 int default_variant(int which) {
     const auto& vs = p2r::variants();
     for (size_t i = 0; i < vs.size(); ++i)
-        if (vs[i].which == which && !vs[i].learned) return (int)i;
+        if (vs[i].which == which && !vs[i].learned && !vs[i].fp64) return (int)i;
     return -1;
 }
 
-int variant_for(p2r_ctx* ctx, int which, int width, const p2r::Variant** out, bool learned = false) {
+int variant_for(p2r_ctx* ctx, int which, int width, const p2r::Variant** out, bool learned = false,
+                bool fp64 = false) {
     const auto& vs = p2r::variants();
     int idx = ctx->chosen[which] >= 0 ? ctx->chosen[which] : default_variant(which);
     if (idx < 0) return fail(P2R_ENOTUNED, "no kernel variant compiled for which=%d", which);
+    if (fp64) {
+        const int w = width != 0 ? width : vs[idx].width;
+        for (const auto& v : vs)
+            if (v.which == which && v.fp64 && v.width == w) { *out = &v; return P2R_OK; }
+        return fail(P2R_ELAYOUT, "no FP64 kernel for width %d", w);
+    }
     if (learned) {
         const int w = width != 0 ? width : vs[idx].width;
         for (const auto& v : vs)
@@ -127,7 +134,7 @@ int variant_for(p2r_ctx* ctx, int which, int width, const p2r::Variant** out, bo
         // first variant of this width (prefer the tuned occupancy/unroll when it matches)
         idx = -1;
         for (size_t i = 0; i < vs.size(); ++i)
-            if (vs[i].which == which && vs[i].width == width && !vs[i].learned) { idx = (int)i; break; }
+            if (vs[i].which == which && vs[i].width == width && !vs[i].learned && !vs[i].fp64) { idx = (int)i; break; }
         if (idx < 0) return fail(P2R_ELAYOUT, "layout width %d not supported (32, 64, 128, 256 for p2r; 64 for p2z)", width);
     }
     (void)0;
@@ -154,6 +161,8 @@ int check_opts(const p2r_opts* o) {
     if (std::isnan(o->chi2_cut)) return fail(P2R_EINVAL, "chi2_cut is NaN");
     if (o->fp64_fallback < 0 || o->fp64_fallback > 3) return fail(P2R_EINVAL, "fp64_fallback must be 0, 1, 2 or 3");
     if (o->cyl_start < 0 || o->cyl_start > 1) return fail(P2R_EINVAL, "cyl_start must be 0 or 1");
+    if (o->fp64 < 0 || o->fp64 > 1) return fail(P2R_EINVAL, "fp64 must be 0 or 1");
+    if (o->fp64 && o->mlp) return fail(P2R_EINVAL, "the learned start runs in FP32 only (fp64 = 1 with an mlp)");
     return P2R_OK;
 }
 
@@ -217,6 +226,7 @@ void p2r_opts_default(p2r_opts* o) {
     o->use_graph = 1;
     o->helix_evals = nullptr;
     o->cyl_start = 0;
+    o->fp64 = 0;
 }
 
 int p2r_ctx_create(p2r_ctx** out, int device, const char* tune_cache_path) {
@@ -266,7 +276,7 @@ int p2r_layout_width(p2r_ctx* ctx, int which, int32_t* W_out) {
 const char* p2r_variant_at(int which, int i) {
     int k = 0;
     for (const auto& v : p2r::variants())
-        if (v.which == which && !v.learned && k++ == i) return v.name;
+        if (v.which == which && !v.learned && !v.fp64 && k++ == i) return v.name;
     return nullptr;
 }
 
@@ -275,7 +285,7 @@ int p2r_set_variant(p2r_ctx* ctx, int which, const char* name) {
     if (which < 0 || which > 2) return fail(P2R_EINVAL, "which must be 0 (p2r), 1 (p2z) or 2 (ragged)");
     if (!name) return fail(P2R_EINVAL, "name is NULL");
     const p2r::Variant* v = find_variant(which, name);
-    if (!v || v->learned) return fail(P2R_ENOTUNED, "no plain kernel variant named '%s' for which=%d", name, which);
+    if (!v || v->learned || v->fp64) return fail(P2R_ENOTUNED, "no plain kernel variant named '%s' for which=%d", name, which);
     ctx->chosen[which] = (int)(v - p2r::variants().data());
     return P2R_OK;
 }
@@ -308,7 +318,7 @@ static int propagate_common(int which, p2r_ctx* ctx, const p2r_opts* opts, int32
     const p2r::Variant* v = nullptr;
     const p2r_mlp* mlp = static_cast<const p2r_mlp*>(opts->mlp);
     if (mlp && mlp->device != ctx->device) return fail(P2R_EINVAL, "mlp lives on device %d, context on %d", mlp->device, ctx->device);
-    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v, mlp != nullptr);
+    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v, mlp != nullptr, opts->fp64 != 0);
     if (rc) return rc;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
@@ -358,7 +368,7 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     for (const void* p : a4)
         if (p && !aligned(p, 4)) return fail(P2R_ELAYOUT, "buffer not 4-byte aligned");
     const p2r::Variant* v = nullptr;
-    rc = variant_for(ctx, 2, 0, &v);
+    rc = variant_for(ctx, 2, 0, &v, false, opts->fp64 != 0);
     if (rc) return rc;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
@@ -399,7 +409,7 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     }
     if (!ctx->rag_work && (e = hipMalloc(&ctx->rag_work, sizeof(int32_t))) != hipSuccess)
         return hip_fail(e, "hipMalloc");
-    const int slot = v->waves_per_eu == 4 ? 1 : 0;
+    const int slot = v->fp64 ? 2 : (v->waves_per_eu == 4 ? 1 : 0);
     if (ctx->rag_blocks_per_cu[slot] == 0) {
         int nb = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, p2r::RAG_W, 0);
@@ -692,7 +702,7 @@ int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, vo
     int best_i = -1;
     int cur_w = -1;
     for (size_t i = 0; i < vs.size(); ++i) {
-        if (vs[i].which != which || vs[i].learned) continue;
+        if (vs[i].which != which || vs[i].learned || vs[i].fp64) continue;
         if (vs[i].width != cur_w) {
             TRY(p2r::launch_synth(which, vs[i].width, n_tracks, n_layers, surf, trk, hits, s), "synthetic fill");
             cur_w = vs[i].width;

@@ -9,20 +9,23 @@
 
 namespace p2r {
 
-__device__ __forceinline__ void load_track(const float* __restrict__ t, int W, State& st) {
+template <typename T>
+__device__ __forceinline__ void load_track(const float* __restrict__ t, int W, StateT<T>& st) {
 #pragma unroll
-    for (int f = 0; f < 6; ++f) st.p[f] = t[f * W];
+    for (int f = 0; f < 6; ++f) st.p[f] = (T)t[f * W];
 #pragma unroll
-    for (int f = 0; f < 21; ++f) st.c[f] = t[(6 + f) * W];
-    st.q = t[27 * W];
+    for (int f = 0; f < 21; ++f) st.c[f] = (T)t[(6 + f) * W];
+    st.q = (T)t[27 * W];
 }
 
-__device__ __forceinline__ void store_track(float* __restrict__ t, int W, const State& st) {
+// results are stored in FP32 whatever the arithmetic type
+template <typename T>
+__device__ __forceinline__ void store_track(float* __restrict__ t, int W, const StateT<T>& st) {
 #pragma unroll
-    for (int f = 0; f < 6; ++f) t[f * W] = st.p[f];
+    for (int f = 0; f < 6; ++f) t[f * W] = (float)st.p[f];
 #pragma unroll
-    for (int f = 0; f < 21; ++f) t[(6 + f) * W] = st.c[f];
-    t[27 * W] = st.q;
+    for (int f = 0; f < 21; ++f) t[(6 + f) * W] = (float)st.c[f];
+    t[27 * W] = (float)st.q;
 }
 
 __device__ __forceinline__ void count_evals(unsigned long long* evals, int iters) {
@@ -37,7 +40,7 @@ __device__ __forceinline__ void count_evals(unsigned long long* evals, int iters
 // start of every helix-to-cylinder solve; the whole wave evaluates it on the
 // matrix cores, so every lane stays in the layer loop (lanes past n shadow
 // the last track and write nothing).
-template <int W, int UNROLL, bool LEARNED>
+template <int W, int UNROLL, bool LEARNED, typename T = float>
 __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, MlpWeights* Wl) {
     if (LEARNED) {
         const uint32_t* s = reinterpret_cast<const uint32_t*>(a.mlp);
@@ -51,11 +54,11 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
     const int g = active ? gid : a.n - 1;
     const int b = g / W, l = g % W;
     const float* tin = a.trk_in + (size_t)b * (28 * W) + l;
-    State st;
+    StateT<T> st;
     load_track(tin, W, st);
     uint32_t flags = 0;
     int nused = 0, evals = 0;
-    float chi2 = 0.0f;
+    T chi2 = 0;
     const bool bad = bad_input(st);
     if (bad) flags = ST_BAD_INPUT;
     if (!bad || LEARNED) {
@@ -65,21 +68,21 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
         for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
 #pragma unroll UNROLL
         for (int ly = 0; ly < a.L; ++ly) {
-            const float m[3] = {hm[0], hm[1], hm[2]};
-            const float V[6] = {hm[3], hm[4], hm[5], hm[6], hm[7], hm[8]};
+            const T m[3] = {hm[0], hm[1], hm[2]};
+            const T V[6] = {hm[3], hm[4], hm[5], hm[6], hm[7], hm[8]};
             if (ly + 1 < a.L) {
                 const float* hn = hb + (size_t)(ly + 1) * (9 * W);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hm[k] = hn[k * W];
             }
-            const float R = a.surf[ly];
-            float s_start = NAN;
+            const T R = a.surf[ly];
+            T s_start = NAN;
             if (LEARNED) {
                 float sphi, cphi;
-                sincosf(st.p[4], &sphi, &cphi);
-                const float w = -st.q * KAPPA * P.bz * st.p[3];
+                sincosf((float)st.p[4], &sphi, &cphi);
+                const float w = (float)(-st.q * KAPPA * P.bz * st.p[3]);
                 float feat[MLP_IN], sl;
-                const bool ok = mlp_features_of(st.p[0], st.p[1], cphi, sphi, w, R, feat, sl);
+                const bool ok = mlp_features_of((float)st.p[0], (float)st.p[1], cphi, sphi, w, (float)R, feat, sl);
                 // an offset the compiler cannot see through keeps the weight
                 // reads in LDS inside the loop; hoisted, they would pin ~130
                 // registers for the whole fit
@@ -90,8 +93,8 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
                 if (ok && !bad && finite3(m)) s_start = sl * (1.0f + sinhf(fminf(fmaxf(yv, -8.0f), 8.0f)) * (1.0f / MLP_TARGET_SCALE));
             }
             if (!bad) {
-                float c2 = 0.0f;
-                StepOut o = step_cylinder(st, R, m, V, P, c2, newton_tol(P.tol, R), s_start, MLP_ACCEPT_CM);
+                T c2 = 0;
+                StepOut o = step_cylinder<T>(st, R, m, V, P, c2, newton_tol(P.tol, R), s_start, T(MLP_ACCEPT_CM));
                 flags |= o.flags;
                 evals += o.iters;
                 if (o.updated) { ++nused; chi2 += c2; }
@@ -101,12 +104,12 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
     count_evals(a.evals, active ? evals : 0);
     if (!active) return;
     store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
-    a.chi2[gid] = chi2;
+    a.chi2[gid] = (float)chi2;
     a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
 }
 
 // p2z: W = 64, hits [layer][block][9][64]; disk sign from the input theta
-template <int UNROLL>
+template <int UNROLL, typename T = float>
 __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
     constexpr int W = 64;
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -114,15 +117,15 @@ __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
     const int b = gid / W, l = gid % W;
     const int nb = (a.n + W - 1) / W;
     const float* tin = a.trk_in + (size_t)b * (28 * W) + l;
-    State st;
+    StateT<T> st;
     load_track(tin, W, st);
     uint32_t flags = 0;
     int nused = 0;
-    float chi2 = 0.0f;
+    T chi2 = 0;
     if (bad_input(st)) {
         flags = ST_BAD_INPUT;
     } else {
-        const float zsign = st.p[5] < HALF_PI_F ? 1.0f : -1.0f;
+        const T zsign = (float)st.p[5] < HALF_PI_F ? T(1) : T(-1);
         const size_t lstride = (size_t)nb * (9 * W);
         const float* hb = a.hits + (size_t)b * (9 * W) + l;
         float hm[9];
@@ -130,21 +133,21 @@ __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
         for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
 #pragma unroll UNROLL
         for (int ly = 0; ly < a.L; ++ly) {
-            const float m[3] = {hm[0], hm[1], hm[2]};
-            const float V[6] = {hm[3], hm[4], hm[5], hm[6], hm[7], hm[8]};
+            const T m[3] = {hm[0], hm[1], hm[2]};
+            const T V[6] = {hm[3], hm[4], hm[5], hm[6], hm[7], hm[8]};
             if (ly + 1 < a.L) {
                 const float* hn = hb + (size_t)(ly + 1) * lstride;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hm[k] = hn[k * W];
             }
-            float c2 = 0.0f;
-            StepOut o = step_plane(st, zsign * a.surf[ly], m, V, P, c2);
+            T c2 = 0;
+            StepOut o = step_plane<T>(st, zsign * T(a.surf[ly]), m, V, P, c2);
             flags |= o.flags;
             if (o.updated) { ++nused; chi2 += c2; }
         }
     }
     store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
-    a.chi2[gid] = chi2;
+    a.chi2[gid] = (float)chi2;
     a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
 }
 
@@ -179,13 +182,27 @@ P2R_LEARNED_KERNEL(64, 0, 1)
 P2R_LEARNED_KERNEL(128, 0, 1)
 P2R_LEARNED_KERNEL(256, 0, 1)
 P2R_LEARNED_KERNEL(32, 0, 1)
+// FP64 fits: every step in FP64 on the same FP32 inputs, results rounded to
+// FP32 (a precision and throughput reference for the FP32 kernels)
+#define P2R_F64_KERNEL(W)                                                                 \
+    __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256)))               \
+    p2r_f64_w##W(FitLaunch a, Params P) { p2r_body<W, 1, false, double>(a, P, nullptr); }
+P2R_F64_KERNEL(32)
+P2R_F64_KERNEL(64)
+P2R_F64_KERNEL(128)
+P2R_F64_KERNEL(256)
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256))) p2z_f64_w64(FitLaunch a, Params P) {
+    p2z_body<1, double>(a, P);
+}
+
 P2Z_KERNEL(0, 1)
 P2Z_KERNEL(4, 1)
 P2Z_KERNEL(5, 1)
 P2Z_KERNEL(0, 2)
 
-#define VAR(WH, W, E, U, K) Variant{WH, W, E, U, #K, (const void*)&K, false}
-#define VARL(W, E, U, K) Variant{0, W, E, U, #K, (const void*)&K, true}
+#define VAR(WH, W, E, U, K) Variant{WH, W, E, U, #K, (const void*)&K, false, false}
+#define VARL(W, E, U, K) Variant{0, W, E, U, #K, (const void*)&K, true, false}
+#define VARD(WH, W, K) Variant{WH, W, 0, 1, #K, (const void*)&K, false, true}
 
 const void* ragged_fit_symbol(int wpe);   // ragged.hip
 
@@ -204,8 +221,14 @@ const std::vector<Variant>& variants() {
         VAR(1, 64, 4, 1, p2z_w64_e4_u1),
         VAR(1, 64, 5, 1, p2z_w64_e5_u1),
         VAR(1, 64, 0, 2, p2z_w64_e0_u2),
-        Variant{2, RAG_W, 0, 1, "rag_fit_e0", ragged_fit_symbol(0), false},   // default ragged
-        Variant{2, RAG_W, 4, 1, "rag_fit_e4", ragged_fit_symbol(4), false},
+        Variant{2, RAG_W, 0, 1, "rag_fit_e0", ragged_fit_symbol(0), false, false},   // default ragged
+        Variant{2, RAG_W, 4, 1, "rag_fit_e4", ragged_fit_symbol(4), false, false},
+        Variant{2, RAG_W, 0, 1, "rag_fit_f64", ragged_fit_symbol(-1), false, true},
+        VARD(0, 64, p2r_f64_w64),          // FP64 fits, one per width
+        VARD(0, 32, p2r_f64_w32),
+        VARD(0, 128, p2r_f64_w128),
+        VARD(0, 256, p2r_f64_w256),
+        VARD(1, 64, p2z_f64_w64),
         VARL(64, 0, 1, p2r_mlp_w64_e0_u1),     // learned start, one per width
         VARL(128, 0, 1, p2r_mlp_w128_e0_u1),
         VARL(256, 0, 1, p2r_mlp_w256_e0_u1),
@@ -272,7 +295,7 @@ __global__ void synth_kernel(int which, int W, int32_t n, int32_t L, float* surf
         float sphi, cphi;
         sincosf(ph, &sphi, &cphi);
         if (alive) {
-            HelixPt h;
+            HelixT<float> h;
             float s = 0.0f;
             int it = 0;
             bool ok, lok;

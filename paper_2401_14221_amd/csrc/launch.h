@@ -19,6 +19,7 @@ struct Variant {
     const char* name;
     const void* fn;   // kernel symbol
     bool learned;     // p2r with the MLP start
+    bool fp64;        // every step in FP64 (FP32 inputs and results)
 };
 
 const std::vector<Variant>& variants();

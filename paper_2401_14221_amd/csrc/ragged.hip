@@ -240,24 +240,25 @@ __global__ void __launch_bounds__(256) rag_pack(RaggedLaunch a) {
     }
 }
 
+template <typename T>
 __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Params& P, int b, int lane) {
     const int64_t p = (int64_t)b * RAG_W + lane;
     if (p >= a.n) return;
     const int t = a.perm[p];
-    State st;
+    StateT<T> st;
 #pragma unroll
     for (int f = 0; f < 6; ++f) st.p[f] = a.par_in[(size_t)t * 6 + f];
 #pragma unroll
     for (int f = 0; f < 21; ++f) st.c[f] = a.cov_in[(size_t)t * 21 + f];
     const int qi = a.q[t];
-    st.q = (float)qi;
+    st.q = (T)qi;
     const int64_t h0 = a.offsets[t];
     const int64_t L = a.offsets[t + 1] - h0;
     const int64_t o = a.blk_off[b];
     const int rows = a.blk_off[b + 1] - (int32_t)o;
     uint32_t flags = 0;
     int nused = 0;
-    float chi2 = 0.0f;
+    T chi2 = 0;
     if (L < 0 || L > a.lmax || h0 < 0 || h0 + L > a.n_hits || L > rows || (qi != 1 && qi != -1) ||
         bad_input(st)) {
         flags = ST_BAD_INPUT;
@@ -269,20 +270,21 @@ __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Pa
             for (int f = 0; f < RAG_FIELDS; ++f) hb[f] = src[f * RAG_W];
         }
         for (int j = 0; j < (int)L; ++j) {
-            const float type = hb[0], v = hb[1];
-            const float m[3] = {hb[2], hb[3], hb[4]};
-            const float V[6] = {hb[5], hb[6], hb[7], hb[8], hb[9], hb[10]};
+            const float type = hb[0];
+            const T v = hb[1];
+            const T m[3] = {hb[2], hb[3], hb[4]};
+            const T V[6] = {hb[5], hb[6], hb[7], hb[8], hb[9], hb[10]};
             if (j + 1 < (int)L) {
                 const float* nx = src + (size_t)(j + 1) * (RAG_FIELDS * RAG_W);
 #pragma unroll
                 for (int f = 0; f < RAG_FIELDS; ++f) hb[f] = nx[f * RAG_W];
             }
-            float c2 = 0.0f;
+            T c2 = 0;
             StepOut out;
             if (type == 0.0f) {
-                out = step_cylinder(st, v, m, V, P, c2, newton_tol(P.tol, v), NAN);
+                out = step_cylinder<T>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
             } else if (type == 1.0f) {
-                out = step_plane(st, v, m, V, P, c2);
+                out = step_plane<T>(st, v, m, V, P, c2);
             } else {
                 out = StepOut{ST_BAD_INPUT, false, 0};
             }
@@ -291,16 +293,16 @@ __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Pa
         }
     }
 #pragma unroll
-    for (int f = 0; f < 6; ++f) a.par_out[(size_t)t * 6 + f] = st.p[f];
+    for (int f = 0; f < 6; ++f) a.par_out[(size_t)t * 6 + f] = (float)st.p[f];
 #pragma unroll
-    for (int f = 0; f < 21; ++f) a.cov_out[(size_t)t * 21 + f] = st.c[f];
-    a.chi2[t] = chi2;
+    for (int f = 0; f < 21; ++f) a.cov_out[(size_t)t * 21 + f] = (float)st.c[f];
+    a.chi2[t] = (float)chi2;
     a.status[t] = flags | ST_DONE | ((uint32_t)(nused > 255 ? 255 : nused) << NUSED_SHIFT);
 }
 
 // Every wave leaves the loop once the counter passes the last block, so the
 // grid drains whatever its size.
-template <int WPE>
+template <int WPE, typename T>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 rag_fit(RaggedLaunch a, Params P) {
     const int lane = threadIdx.x;
@@ -309,15 +311,18 @@ rag_fit(RaggedLaunch a, Params P) {
         if (lane == 0) b = atomicAdd(a.work, 1);
         b = __shfl(b, 0);
         if (b >= a.nb) break;
-        fit_sorted_track(a, P, b, lane);
+        fit_sorted_track<T>(a, P, b, lane);
     }
 }
 
-template __global__ void rag_fit<0>(RaggedLaunch, Params);
-template __global__ void rag_fit<4>(RaggedLaunch, Params);
+template __global__ void rag_fit<0, float>(RaggedLaunch, Params);
+template __global__ void rag_fit<4, float>(RaggedLaunch, Params);
+template __global__ void rag_fit<0, double>(RaggedLaunch, Params);
 
+// wpe 0 or 4: the FP32 fit at that occupancy target; -1: the FP64 fit
 const void* ragged_fit_symbol(int wpe) {
-    return wpe == 4 ? (const void*)&rag_fit<4> : (const void*)&rag_fit<0>;
+    if (wpe < 0) return (const void*)&rag_fit<0, double>;
+    return wpe == 4 ? (const void*)&rag_fit<4, float> : (const void*)&rag_fit<0, float>;
 }
 
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s) {

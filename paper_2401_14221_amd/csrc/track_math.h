@@ -1,4 +1,5 @@
-// Device arithmetic of one track-layer step in FP32, one lane per track.
+// Device arithmetic of one track-layer step, one lane per track, in FP32
+// (the fit) or FP64 (the FP64 fit, every function templated on the type).
 //
 // State p = (x, y, z, ipt = 1/pT, phi, theta), charge q; covariance kept
 // packed as 21 registers (lower triangle, row-major).  The step follows the
@@ -39,6 +40,8 @@ constexpr int NUSED_SHIFT = 8;
 // is treated as singular.
 constexpr float PD_TAU32 = 1e-3f;
 constexpr double PD_TAU64 = 1e-6;
+// The FP64 fit (every step in FP64) takes the oracle's threshold.
+constexpr double PD_TAU_F64_FIT = 1e-12;
 
 // Reciprocal and quotient: v_rcp_f32 (1 ulp) followed by one Newton
 // correction of the result, r + r (1 - b r) and q + r (a - b q) with the
@@ -91,6 +94,21 @@ __device__ __forceinline__ void sincos_fit(float x, float* sn, float* cs) {
     *cs = ((q + 1) & 2) ? -b : b;
 }
 
+// Numeric helpers of the templated arithmetic below: FP32 uses the short
+// forms above, FP64 the library's correctly rounded ones.
+__device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float div_(float a, float b) { return fdiv(a, b); }
+__device__ __forceinline__ double div_(double a, double b) { return a / b; }
+__device__ __forceinline__ float rcp_(float b) { return frcp(b); }
+__device__ __forceinline__ double rcp_(double b) { return 1.0 / b; }
+__device__ __forceinline__ float sqrt_start_(float x) { return sqrt_start(x); }
+__device__ __forceinline__ double sqrt_start_(double x) { return sqrt(x); }
+__device__ __forceinline__ void sincos_(float x, float* s, float* c) { sincos_fit(x, s, c); }
+__device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
+template <typename T> __device__ __forceinline__ constexpr T pi_() { return T(3.14159265358979323846); }
+template <typename T> __device__ __forceinline__ constexpr T two_pi_() { return T(6.28318530717958647692); }
+
 // packed index of (i, j), j <= i
 constexpr int I21(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
@@ -103,11 +121,13 @@ struct Params {
     int32_t start_mode;   // cylinder start: 0 straight line (plain), 1 closed form
 };
 
-struct State {
-    float p[6];
-    float c[21];
-    float q;
+template <typename T>
+struct StateT {
+    T p[6];
+    T c[21];
+    T q;
 };
+using State = StateT<float>;
 
 // ---------------------------------------------------------------- helix
 // Point of the helix at transverse path s, in the half-angle form
@@ -115,12 +135,13 @@ struct State {
 //   x' = x + chord cos(phi_m),  y' = y + chord sin(phi_m),  phi' = phi + 2u,
 // which is exact and free of cancellation as omega -> 0.  For |u| < 0.5 the
 // sines and cosines of u come from their Taylor series (error < 1e-10).
-struct HelixPt {
-    float x, y;          // position at s
-    float cm, sm;        // cos, sin of phi + u
-    float cp, sp;        // cos, sin of phi' = phi + 2u
-    float chord, S, dS;  // s sinc(u), sinc(u), d sinc/du
-    float u;
+template <typename T>
+struct HelixT {
+    T x, y;          // position at s
+    T cm, sm;        // cos, sin of phi + u
+    T cp, sp;        // cos, sin of phi' = phi + 2u
+    T chord, S, dS;  // s sinc(u), sinc(u), d sinc/du
+    T u;
 };
 
 __device__ __forceinline__ void sinc_terms(float u, float& su, float& cu, float& S, float& dS) {
@@ -139,16 +160,33 @@ __device__ __forceinline__ void sinc_terms(float u, float& su, float& cu, float&
     }
 }
 
-__device__ __forceinline__ void helix_at(float x, float y, float cphi, float sphi, float w, float s, HelixPt& h) {
-    float u = 0.5f * w * s;
-    float su, cu;
+// FP64: the series only for |u| < 1e-3 (truncation below 1e-25), the
+// library's sin and cos above.
+__device__ __forceinline__ void sinc_terms(double u, double& su, double& cu, double& S, double& dS) {
+    if (fabs(u) < 1e-3) {
+        const double u2 = u * u;
+        S = 1.0 + u2 * (-1.0 / 6.0 + u2 * (1.0 / 120.0 + u2 * (-1.0 / 5040.0)));
+        cu = 1.0 + u2 * (-0.5 + u2 * (1.0 / 24.0 + u2 * (-1.0 / 720.0 + u2 * (1.0 / 40320.0))));
+        dS = u * (-1.0 / 3.0 + u2 * (1.0 / 30.0 + u2 * (-1.0 / 840.0 + u2 * (1.0 / 45360.0))));
+        su = u * S;
+    } else {
+        sincos(u, &su, &cu);
+        S = su / u;
+        dS = (cu - S) / u;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void helix_at(T x, T y, T cphi, T sphi, T w, T s, HelixT<T>& h) {
+    T u = T(0.5) * w * s;
+    T su, cu;
     sinc_terms(u, su, cu, h.S, h.dS);
     h.u = u;
     h.chord = s * h.S;
     h.cm = cphi * cu - sphi * su;
     h.sm = sphi * cu + cphi * su;
-    h.x = fmaf(h.chord, h.cm, x);
-    h.y = fmaf(h.chord, h.sm, y);
+    h.x = fma_(h.chord, h.cm, x);
+    h.y = fma_(h.chord, h.sm, y);
     h.cp = h.cm * cu - h.sm * su;
     h.sp = h.sm * cu + h.cm * su;
 }
@@ -160,12 +198,13 @@ __device__ __forceinline__ void helix_at(float x, float y, float cphi, float sph
 // d^2 = r0^2 - 2 a'/w + rho^2, a' = x sin(phi) - y cos(phi), this reads
 //   |w| (R^2 - r0^2) <= 2 (R - sign(w) a')  and  |w| (r0^2 - R^2) <= 2 (R + sign(w) a'),
 // which at w = 0 reduces to the line's distance test |a'| <= R.
-__device__ __forceinline__ bool cylinder_reachable(float x, float y, float cphi, float sphi, float w, float R) {
-    float r0sq = fmaf(x, x, y * y);
-    float ap = x * sphi - y * cphi;
-    float sg = w >= 0.0f ? 1.0f : -1.0f;
-    float t = fabsf(w) * (R * R - r0sq);
-    return t <= 2.0f * (R - sg * ap) && -t <= 2.0f * (R + sg * ap);
+template <typename T>
+__device__ __forceinline__ bool cylinder_reachable(T x, T y, T cphi, T sphi, T w, T R) {
+    T r0sq = fma_(x, x, y * y);
+    T ap = x * sphi - y * cphi;
+    T sg = w >= T(0.0) ? T(1.0) : -T(1.0);
+    T t = fabs(w) * (R * R - r0sq);
+    return t <= T(2.0) * (R - sg * ap) && -t <= T(2.0) * (R + sg * ap);
 }
 
 // How far behind the start a surface may lie and still be the next one
@@ -177,22 +216,23 @@ constexpr float BACK_TOL = 1.0f;
 // b = x cos(phi) + y sin(phi) and d = R^2 - r0^2 the roots are
 // -b -/+ sqrt(b^2 + d), each taken in its cancellation-free form.  *ok is
 // false when no root lies beyond -BACK_TOL.
-__device__ __forceinline__ float line_path(float x, float y, float cphi, float sphi, float R, bool* ok) {
-    float b = x * cphi + y * sphi;
-    float r0sq = fmaf(x, x, y * y);
-    float dr2 = R * R - r0sq;
-    float disc = fmaf(b, b, dr2);
-    float sq = sqrt_start(fmaxf(disc, 0.0f));
-    float lo, hi;   // lo <= hi
-    if (b >= 0.0f) {
+template <typename T>
+__device__ __forceinline__ T line_path(T x, T y, T cphi, T sphi, T R, bool* ok) {
+    T b = x * cphi + y * sphi;
+    T r0sq = fma_(x, x, y * y);
+    T dr2 = R * R - r0sq;
+    T disc = fma_(b, b, dr2);
+    T sq = sqrt_start_(fmax(disc, T(0.0)));
+    T lo, hi;   // lo <= hi
+    if (b >= T(0.0)) {
         lo = -(b + sq);
-        hi = (b + sq) > 0.0f ? fdiv(dr2, b + sq) : 0.0f;
+        hi = (b + sq) > T(0.0) ? div_(dr2, b + sq) : T(0.0);
     } else {
-        lo = fdiv(dr2, b - sq);
+        lo = div_(dr2, b - sq);
         hi = sq - b;
     }
-    *ok = disc >= 0.0f && hi > -BACK_TOL;
-    return lo > -BACK_TOL ? lo : hi;
+    *ok = disc >= T(0.0) && hi > -T(BACK_TOL);
+    return lo > -T(BACK_TOL) ? lo : hi;
 }
 
 // Closed-form crossing of |xy| = R within half a turn, in FP32 without
@@ -212,30 +252,39 @@ __device__ __forceinline__ float atan_ratio(float t) {   // atan(t) / t
     return fdiv(atanf(t), t);
 }
 
-__device__ __forceinline__ bool closed_form_cylinder(float x, float y, float cphi, float sphi, float w, float R,
-                                                     float& s_out) {
-    float b = x * cphi + y * sphi;
-    float a = y * cphi - x * sphi;
-    float d = R * R - fmaf(x, x, y * y);
-    float alpha = 1.0f + a * w - 0.25f * w * w * d;
-    float disc = fmaf(b, b, alpha * d);
-    if (disc < 0.0f) return false;
-    float sq = sqrt_start(disc);
-    float den[2] = {b + sq, b - sq};
+__device__ __forceinline__ double atan_ratio(double t) {   // atan(t) / t in FP64
+    if (fabs(t) < 1e-3) {
+        const double t2 = t * t;
+        return 1.0 + t2 * (-1.0 / 3.0 + t2 * (1.0 / 5.0 + t2 * (-1.0 / 7.0)));
+    }
+    return atan(t) / t;
+}
+
+template <typename T>
+__device__ __forceinline__ bool closed_form_cylinder(T x, T y, T cphi, T sphi, T w, T R,
+                                                     T& s_out) {
+    T b = x * cphi + y * sphi;
+    T a = y * cphi - x * sphi;
+    T d = R * R - fma_(x, x, y * y);
+    T alpha = T(1.0) + a * w - T(0.25) * w * w * d;
+    T disc = fma_(b, b, alpha * d);
+    if (disc < T(0.0)) return false;
+    T sq = sqrt_start_(disc);
+    T den[2] = {b + sq, b - sq};
     bool have = false;
-    float best = 0.0f;
+    T best = T(0.0);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        float s;
-        if (den[k] == 0.0f) {
-            if (w == 0.0f) continue;             // line root at infinity
-            s = fdiv(PI_F, fabsf(w));            // t = +-inf: exactly half a turn
+        T s;
+        if (den[k] == T(0.0)) {
+            if (w == T(0.0)) continue;             // line root at infinity
+            s = div_(pi_<T>(), fabs(w));            // t = +-inf: exactly half a turn
         } else {
-            float c = fdiv(d, den[k]);
-            float t = 0.5f * w * c;
+            T c = div_(d, den[k]);
+            T t = T(0.5) * w * c;
             s = c * atan_ratio(t);
         }
-        if (s > -BACK_TOL && (!have || s < best)) { best = s; have = true; }
+        if (s > -T(BACK_TOL) && (!have || s < best)) { best = s; have = true; }
     }
     s_out = best;
     return have;
@@ -245,19 +294,20 @@ __device__ __forceinline__ bool closed_form_cylinder(float x, float y, float cph
 // from s0 (the straight-line root or a proposal).  Stops when |f| <= tol; returns false
 // after max_iter helix evaluations without convergence.  h holds the last
 // evaluation.
-__device__ __forceinline__ bool newton_cylinder(float x, float y, float cphi, float sphi, float w, float R,
-                                                float tol, int max_iter, float s0, float& s, HelixPt& h,
+template <typename T>
+__device__ __forceinline__ bool newton_cylinder(T x, T y, T cphi, T sphi, T w, T R,
+                                                T tol, int max_iter, T s0, T& s, HelixT<T>& h,
                                                 int& iters, bool have_first = false) {
-    const float invR = frcp(R);
-    const float inv2R = 0.5f * invR;
+    const T invR = rcp_(R);
+    const T inv2R = T(0.5) * invR;
     s = s0;
     for (int it = 0; it < max_iter; ++it) {
         if (!(have_first && it == 0)) helix_at(x, y, cphi, sphi, w, s, h);
-        float f = (fmaf(h.x, h.x, h.y * h.y) - R * R) * inv2R;
+        T f = (fma_(h.x, h.x, h.y * h.y) - R * R) * inv2R;
         iters = it + 1;
-        if (fabsf(f) <= tol) return true;
-        float fp = (h.x * h.cp + h.y * h.sp) * invR;
-        s -= fdiv(f, fp);
+        if (fabs(f) <= tol) return true;
+        T fp = (h.x * h.cp + h.y * h.sp) * invR;
+        s -= div_(f, fp);
     }
     return false;
 }
@@ -270,72 +320,75 @@ __device__ __forceinline__ bool newton_cylinder(float x, float y, float cphi, fl
 //   dphi'/domega = s,  dz'/dtheta = -s / sin^2 theta,  d(x', y', z', phi')/ds = (cos phi', sin phi', cot theta, omega)
 // The path s*(p) to the surface adds (d state/ds) (ds*/dp)^T, with
 // ds*/dp = -(dg/dp) / (dg/ds) for the surface constraint g(state(p, s)) = 0.
-struct Jac {
+template <typename T>
+struct JacT {
     // rows x, y, phi: columns x, y, z, ipt, phi, theta (some are structurally 0)
-    float a[3][6];
+    T a[3][6];
     // row z: columns x, y, z, ipt, phi, theta
-    float z[6];
+    T z[6];
 };
 
 // Cylinder: g = x'^2 + y'^2 - R^2, dg/ds = 2 D, D = x' cos phi' + y' sin phi'.
 // ds/dx = -x'/D, ds/dy = -y'/D, ds/dphi = -(x' y - x y')/D,
 // ds/dipt = -kq (x' dx'/domega + y' dy'/domega)/D, ds/dz = ds/dtheta = 0.
-__device__ __forceinline__ void jacobian_cylinder(float x, float y, float w, float kq, float s, float cot,
-                                                  float sinth, const HelixPt& h, Jac& J) {
-    float hs2 = 0.5f * s * s;
-    float dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
-    float dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
-    float iD = frcp(h.x * h.cp + h.y * h.sp);
-    float dsx = -h.x * iD;
-    float dsy = -h.y * iD;
-    float dsphi = -(h.x * y - x * h.y) * iD;
-    float dsipt = -kq * (h.x * dxw + h.y * dyw) * iD;
+template <typename T>
+__device__ __forceinline__ void jacobian_cylinder(T x, T y, T w, T kq, T s, T cot,
+                                                  T sinth, const HelixT<T>& h, JacT<T>& J) {
+    T hs2 = T(0.5) * s * s;
+    T dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
+    T dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
+    T iD = rcp_(h.x * h.cp + h.y * h.sp);
+    T dsx = -h.x * iD;
+    T dsy = -h.y * iD;
+    T dsphi = -(h.x * y - x * h.y) * iD;
+    T dsipt = -kq * (h.x * dxw + h.y * dyw) * iD;
     // x' row
-    J.a[0][0] = fmaf(h.cp, dsx, 1.0f);
+    J.a[0][0] = fma_(h.cp, dsx, T(1.0));
     J.a[0][1] = h.cp * dsy;
-    J.a[0][2] = 0.0f;
-    J.a[0][3] = fmaf(h.cp, dsipt, kq * dxw);
-    J.a[0][4] = fmaf(h.cp, dsphi, -h.chord * h.sm);
-    J.a[0][5] = 0.0f;
+    J.a[0][2] = T(0.0);
+    J.a[0][3] = fma_(h.cp, dsipt, kq * dxw);
+    J.a[0][4] = fma_(h.cp, dsphi, -h.chord * h.sm);
+    J.a[0][5] = T(0.0);
     // y' row
     J.a[1][0] = h.sp * dsx;
-    J.a[1][1] = fmaf(h.sp, dsy, 1.0f);
-    J.a[1][2] = 0.0f;
-    J.a[1][3] = fmaf(h.sp, dsipt, kq * dyw);
-    J.a[1][4] = fmaf(h.sp, dsphi, h.chord * h.cm);
-    J.a[1][5] = 0.0f;
+    J.a[1][1] = fma_(h.sp, dsy, T(1.0));
+    J.a[1][2] = T(0.0);
+    J.a[1][3] = fma_(h.sp, dsipt, kq * dyw);
+    J.a[1][4] = fma_(h.sp, dsphi, h.chord * h.cm);
+    J.a[1][5] = T(0.0);
     // phi' row
     J.a[2][0] = w * dsx;
     J.a[2][1] = w * dsy;
-    J.a[2][2] = 0.0f;
-    J.a[2][3] = fmaf(w, dsipt, kq * s);
-    J.a[2][4] = fmaf(w, dsphi, 1.0f);
-    J.a[2][5] = 0.0f;
+    J.a[2][2] = T(0.0);
+    J.a[2][3] = fma_(w, dsipt, kq * s);
+    J.a[2][4] = fma_(w, dsphi, T(1.0));
+    J.a[2][5] = T(0.0);
     // z' row
     J.z[0] = cot * dsx;
     J.z[1] = cot * dsy;
-    J.z[2] = 1.0f;
+    J.z[2] = T(1.0);
     J.z[3] = cot * dsipt;
     J.z[4] = cot * dsphi;
-    J.z[5] = -fdiv(s, sinth * sinth);
+    J.z[5] = -div_(s, sinth * sinth);
 }
 
 // Plane: g = z' - Z; ds/dz = -tan(theta), ds/dtheta = s / (sin cos), others 0.
 // The z' row vanishes (z' = Z).
-__device__ __forceinline__ void jacobian_plane(float w, float kq, float s, float tanth, float sinth, float costh,
-                                               const HelixPt& h, Jac& J) {
-    float hs2 = 0.5f * s * s;
-    float dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
-    float dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
-    float dsz = -tanth;
-    float dsth = fdiv(s, sinth * costh);
-    J.a[0][0] = 1.0f;  J.a[0][1] = 0.0f;  J.a[0][2] = h.cp * dsz;  J.a[0][3] = kq * dxw;
+template <typename T>
+__device__ __forceinline__ void jacobian_plane(T w, T kq, T s, T tanth, T sinth, T costh,
+                                               const HelixT<T>& h, JacT<T>& J) {
+    T hs2 = T(0.5) * s * s;
+    T dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
+    T dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
+    T dsz = -tanth;
+    T dsth = div_(s, sinth * costh);
+    J.a[0][0] = T(1.0);  J.a[0][1] = T(0.0);  J.a[0][2] = h.cp * dsz;  J.a[0][3] = kq * dxw;
     J.a[0][4] = -h.chord * h.sm;  J.a[0][5] = h.cp * dsth;
-    J.a[1][0] = 0.0f;  J.a[1][1] = 1.0f;  J.a[1][2] = h.sp * dsz;  J.a[1][3] = kq * dyw;
+    J.a[1][0] = T(0.0);  J.a[1][1] = T(1.0);  J.a[1][2] = h.sp * dsz;  J.a[1][3] = kq * dyw;
     J.a[1][4] = h.chord * h.cm;   J.a[1][5] = h.sp * dsth;
-    J.a[2][0] = 0.0f;  J.a[2][1] = 0.0f;  J.a[2][2] = w * dsz;     J.a[2][3] = kq * s;
-    J.a[2][4] = 1.0f;  J.a[2][5] = w * dsth;
-    for (int k = 0; k < 6; ++k) J.z[k] = 0.0f;
+    J.a[2][0] = T(0.0);  J.a[2][1] = T(0.0);  J.a[2][2] = w * dsz;     J.a[2][3] = kq * s;
+    J.a[2][4] = T(1.0);  J.a[2][5] = w * dsth;
+    for (int k = 0; k < 6; ++k) J.z[k] = T(0.0);
 }
 
 // ------------------------------------------------- covariance transport
@@ -344,61 +397,61 @@ __device__ __forceinline__ void jacobian_plane(float w, float kq, float s, float
 // x, y, ipt, phi; row z in all columns (z coefficient 1).  SURF 1 (plane):
 // rows x, y, phi in all columns except (x: y), (y: x), (phi: x, y); row z = 0.
 // The structural zeros are skipped at compile time through the masks.
-template <int SURF>
-__device__ __forceinline__ void transport(const Jac& J, float* c) {
+template <int SURF, typename T>
+__device__ __forceinline__ void transport(const JacT<T>& J, T* c) {
     // column masks of the x, y, phi rows
     constexpr unsigned MX = SURF == 0 ? 0b011011u : 0b111101u;   // bit k: column k used
     constexpr unsigned MY = SURF == 0 ? 0b011011u : 0b111110u;
     constexpr unsigned MP = SURF == 0 ? 0b011011u : 0b111100u;
     // rows of M = J C for the transformed rows x(0), y(1), phi(4), z(2)
-    float M0[6], M1[6], M4[6], M2[6];
+    T M0[6], M1[6], M4[6], M2[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        float m0 = 0.f, m1 = 0.f, m4 = 0.f;
+        T m0 = T(0.), m1 = T(0.), m4 = T(0.);
 #pragma unroll
         for (int l = 0; l < 6; ++l) {
-            if (MX & (1u << l)) m0 = fmaf(J.a[0][l], c[I21(l, k)], m0);
-            if (MY & (1u << l)) m1 = fmaf(J.a[1][l], c[I21(l, k)], m1);
-            if (MP & (1u << l)) m4 = fmaf(J.a[2][l], c[I21(l, k)], m4);
+            if (MX & (1u << l)) m0 = fma_(J.a[0][l], c[I21(l, k)], m0);
+            if (MY & (1u << l)) m1 = fma_(J.a[1][l], c[I21(l, k)], m1);
+            if (MP & (1u << l)) m4 = fma_(J.a[2][l], c[I21(l, k)], m4);
         }
         M0[k] = m0; M1[k] = m1; M4[k] = m4;
         if (SURF == 0) {
-            float m2 = c[I21(2, k)];
+            T m2 = c[I21(2, k)];
 #pragma unroll
             for (int l = 0; l < 6; ++l)
-                if (l != 2) m2 = fmaf(J.z[l], c[I21(l, k)], m2);
+                if (l != 2) m2 = fma_(J.z[l], c[I21(l, k)], m2);
             M2[k] = m2;
         }
     }
     // new rows: r(i) returns the row of M for transformed index i; rows 3, 5 are C's
-    auto Mrow = [&](int i, int k) -> float {
+    auto Mrow = [&](int i, int k) -> T {
         switch (i) {
             case 0: return M0[k];
             case 1: return M1[k];
-            case 2: return SURF == 0 ? M2[k] : 0.0f;
+            case 2: return SURF == 0 ? M2[k] : T(0.0);
             case 4: return M4[k];
             default: return c[I21(i, k)];
         }
     };
-    auto dotJ = [&](int i, int j) -> float {   // (M J^T)_{ij} = sum_k M_ik J_jk
+    auto dotJ = [&](int i, int j) -> T {   // (M J^T)_{ij} = sum_k M_ik J_jk
         if (j == 3 || j == 5) return Mrow(i, j);
         if (j == 2) {
-            if (SURF == 1) return 0.0f;
-            float a = Mrow(i, 2);
+            if (SURF == 1) return T(0.0);
+            T a = Mrow(i, 2);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                if (k != 2) a = fmaf(Mrow(i, k), J.z[k], a);
+                if (k != 2) a = fma_(Mrow(i, k), J.z[k], a);
             return a;
         }
         const unsigned m = j == 0 ? MX : (j == 1 ? MY : MP);
         const int r = j == 0 ? 0 : (j == 1 ? 1 : 2);
-        float a = 0.f;
+        T a = T(0.);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            if (m & (1u << k)) a = fmaf(Mrow(i, k), J.a[r][k], a);
+            if (m & (1u << k)) a = fma_(Mrow(i, k), J.a[r][k], a);
         return a;
     };
-    float n[21];
+    T n[21];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -424,7 +477,7 @@ __device__ __forceinline__ bool inv3_spd(const T s[6], T inv[6], T tau) {
     T det = s[0] * c00 + s[1] * c10 + s[3] * c20;
     bool ok = (s[0] > T(0)) && (c22 > tau * s[0] * s[2]) && (det > tau * s[5] * c22);
     if (!ok) return false;
-    T id = T(1) / det;
+    T id = rcp_(det);
     inv[0] = c00 * id; inv[1] = c10 * id; inv[2] = c11 * id;
     inv[3] = c20 * id; inv[4] = c21 * id; inv[5] = c22 * id;
     return true;
@@ -528,15 +581,19 @@ __device__ __noinline__ uint32_t kalman_update_fp64(Fp64Io* io, float chi2_cut) 
 // A = I and every FMA below returns its accumulator unchanged -- p and C
 // come out bit for bit as they went in.  Branching around it instead makes
 // the compiler copy the whole state into merge registers on every layer.
-__device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], const float V[6],
-                                                  const Params& P, float& chi2, uint32_t& flags) {
-    float* c = st.c;
-    float S[6] = {c[0] + V[0], c[1] + V[1], c[2] + V[2], c[3] + V[3], c[4] + V[4], c[5] + V[5]};
-    float Si[6];
-    const bool pd32 = inv3_spd<float>(S, Si, PD_TAU32);
+template <typename T>
+__device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], const T V[6],
+                                                  const Params& P, T& chi2, uint32_t& flags) {
+    T* c = st.c;
+    T S[6] = {c[0] + V[0], c[1] + V[1], c[2] + V[2], c[3] + V[3], c[4] + V[4], c[5] + V[5]};
+    T Si[6];
+    constexpr bool F32 = sizeof(T) == sizeof(float);
+    const bool pd = inv3_spd<T>(S, Si, F32 ? T(PD_TAU32) : T(PD_TAU_F64_FIT));
     uint32_t res = 0;
     bool done = false;                    // the state was updated by the FP64 path
-    if (P.fp64_fallback == 2 || !pd32) {
+    if (!F32) {
+        if (!pd) res = ST_S_NOT_PD;
+    } else if (P.fp64_fallback == 2 || !pd) {
         if (!P.fp64_fallback) {
             res = ST_S_NOT_PD;
         } else {
@@ -553,7 +610,7 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
                 for (int k = 0; k < 3; ++k) io.m[k] = m[k];
 #pragma unroll
                 for (int k = 0; k < 6; ++k) io.V[k] = V[k];
-                io.chi2 = chi2;
+                io.chi2 = (float)chi2;
                 res = kalman_update_fp64(&io, P.chi2_cut);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) st.p[k] = io.p[k];
@@ -567,45 +624,45 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
                 for (int k = 0; k < 6; ++k) Sd[k] = (double)c[k] + (double)V[k];
                 if (!inv3_spd<double>(Sd, Sid, PD_TAU64)) res = ST_S_NOT_PD;
 #pragma unroll
-                for (int k = 0; k < 6; ++k) Si[k] = (float)Sid[k];
+                for (int k = 0; k < 6; ++k) Si[k] = (T)Sid[k];
             }
         }
     }
-    float r0 = m[0] - st.p[0], r1 = m[1] - st.p[1], r2 = m[2] - st.p[2];
-    float w0 = Si[0] * r0 + Si[1] * r1 + Si[3] * r2;
-    float w1 = Si[1] * r0 + Si[2] * r1 + Si[4] * r2;
-    float w2 = Si[3] * r0 + Si[4] * r1 + Si[5] * r2;
-    float c2 = r0 * w0 + r1 * w1 + r2 * w2;
-    if (res == 0 && !done && P.chi2_cut > 0.0f && c2 > P.chi2_cut) res = ST_CHI2_CUT;
+    T r0 = m[0] - st.p[0], r1 = m[1] - st.p[1], r2 = m[2] - st.p[2];
+    T w0 = Si[0] * r0 + Si[1] * r1 + Si[3] * r2;
+    T w1 = Si[1] * r0 + Si[2] * r1 + Si[4] * r2;
+    T w2 = Si[3] * r0 + Si[4] * r1 + Si[5] * r2;
+    T c2 = r0 * w0 + r1 * w1 + r2 * w2;
+    if (res == 0 && !done && P.chi2_cut > 0.0f && c2 > T(P.chi2_cut)) res = ST_CHI2_CUT;
     const bool apply = res == 0 && !done;
     if (apply) chi2 = c2;
-    w0 = apply ? w0 : 0.0f;
-    w1 = apply ? w1 : 0.0f;
-    w2 = apply ? w2 : 0.0f;
+    w0 = apply ? w0 : T(0.0);
+    w1 = apply ? w1 : T(0.0);
+    w2 = apply ? w2 : T(0.0);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Si[k] = apply ? Si[k] : 0.0f;
+    for (int k = 0; k < 6; ++k) Si[k] = apply ? Si[k] : T(0.0);
     // K = P S^-1 with P = C' H^T (rows c(i,0..2)); KV = K V
-    float K[6][3], KV[6][3];
+    T K[6][3], KV[6][3];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        float p0 = c[I21(i, 0)], p1 = c[I21(i, 1)], p2 = c[I21(i, 2)];
+        T p0 = c[I21(i, 0)], p1 = c[I21(i, 1)], p2 = c[I21(i, 2)];
         K[i][0] = p0 * Si[0] + p1 * Si[1] + p2 * Si[3];
         K[i][1] = p0 * Si[1] + p1 * Si[2] + p2 * Si[4];
         K[i][2] = p0 * Si[3] + p1 * Si[4] + p2 * Si[5];
         KV[i][0] = K[i][0] * V[0] + K[i][1] * V[1] + K[i][2] * V[3];
         KV[i][1] = K[i][0] * V[1] + K[i][1] * V[2] + K[i][2] * V[4];
         KV[i][2] = K[i][0] * V[3] + K[i][1] * V[4] + K[i][2] * V[5];
-        st.p[i] = fmaf(p0, w0, fmaf(p1, w1, fmaf(p2, w2, st.p[i])));
+        st.p[i] = fma_(p0, w0, fma_(p1, w1, fma_(p2, w2, st.p[i])));
     }
     // M = A C' (entries (i, l) with l <= i, and (i, j) with j < 3)
-    auto Mv = [&](int i, int l) -> float {
-        float a = c[I21(i, l)];
-        a = fmaf(-K[i][0], c[I21(0, l)], a);
-        a = fmaf(-K[i][1], c[I21(1, l)], a);
-        a = fmaf(-K[i][2], c[I21(2, l)], a);
+    auto Mv = [&](int i, int l) -> T {
+        T a = c[I21(i, l)];
+        a = fma_(-K[i][0], c[I21(0, l)], a);
+        a = fma_(-K[i][1], c[I21(1, l)], a);
+        a = fma_(-K[i][2], c[I21(2, l)], a);
         return a;
     };
-    float M[6][6];
+    T M[6][6];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -616,20 +673,20 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
     // the rounding residual that the Joseph form exists to absorb; forming
     // it first subtracts the two nearly equal terms exactly (Sterbenz)
     // instead of carrying both through each element's sum.
-    float D[6][3];
+    T D[6][3];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) D[i][j] = KV[i][j] - M[i][j];
-    float n[21];
+    T n[21];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
         for (int l = 0; l <= i; ++l) {
-            float a = M[i][l];
-            a = fmaf(D[i][0], K[l][0], a);
-            a = fmaf(D[i][1], K[l][1], a);
-            a = fmaf(D[i][2], K[l][2], a);
+            T a = M[i][l];
+            a = fma_(D[i][0], K[l][0], a);
+            a = fma_(D[i][1], K[l][1], a);
+            a = fma_(D[i][2], K[l][2], a);
             n[I21(i, l)] = a;
         }
 #pragma unroll
@@ -640,25 +697,28 @@ __device__ __forceinline__ uint32_t kalman_update(State& st, const float m[3], c
 // phi into (-pi, pi].  After a layer phi has moved by at most half a turn
 // plus the update's correction, so one conditional 2 pi step is enough; an
 // input far outside the range takes the general reduction first.
-__device__ __forceinline__ float wrap_phi(float a) {
-    float r = a;
-    if (!(fabsf(r) <= 3.0f * PI_F)) r = a - TWO_PI_F * floorf((a + PI_F) * INV_TWO_PI_F);
-    r = r > PI_F ? r - TWO_PI_F : r;
-    return r <= -PI_F ? r + TWO_PI_F : r;
+template <typename T>
+__device__ __forceinline__ T wrap_phi(T a) {
+    T r = a;
+    if (!(fabs(r) <= T(3.0) * pi_<T>())) r = a - two_pi_<T>() * floor((a + pi_<T>()) * T(0.159154943091895336));
+    r = r > pi_<T>() ? r - two_pi_<T>() : r;
+    return r <= -pi_<T>() ? r + two_pi_<T>() : r;
 }
 
-__device__ __forceinline__ bool finite3(const float m[3]) {
+template <typename T>
+__device__ __forceinline__ bool finite3(const T m[3]) {
     return isfinite(m[0]) && isfinite(m[1]) && isfinite(m[2]);
 }
 
-__device__ __forceinline__ bool bad_input(const State& st) {
+template <typename T>
+__device__ __forceinline__ bool bad_input(const StateT<T>& st) {
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < 6; ++i) bad |= !isfinite(st.p[i]);
 #pragma unroll
     for (int i = 0; i < 21; ++i) bad |= !isfinite(st.c[i]);
-    bad |= !(st.p[3] > 0.0f);
-    bad |= !(st.p[5] > 0.0f && st.p[5] < PI_F);
+    bad |= !(st.p[3] > T(0.0));
+    bad |= !(st.p[5] > T(0.0) && st.p[5] < pi_<T>());
     return bad;
 }
 
@@ -672,16 +732,17 @@ struct StepOut {
     int iters;
 };
 
-__device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float m[3], const float V[6],
-                                                 const Params& P, float& chi2, float tol, float s_start,
-                                                 float accept_cm = 0.0f) {
+template <typename T>
+__device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3], const T V[6],
+                                                 const Params& P, T& chi2, T tol, T s_start,
+                                                 T accept_cm = T(0.0)) {
     StepOut o{0u, false, 0};
     if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
-    float x = st.p[0], y = st.p[1];
-    float sphi, cphi;
-    sincos_fit(st.p[4], &sphi, &cphi);
-    float kq = -st.q * KAPPA * P.bz;
-    float w = kq * st.p[3];
+    T x = st.p[0], y = st.p[1];
+    T sphi, cphi;
+    sincos_(st.p[4], &sphi, &cphi);
+    T kq = -st.q * T(2.99792458e-3) * P.bz;
+    T w = kq * st.p[3];
     if (!cylinder_reachable(x, y, cphi, sphi, w, R)) { o.flags = ST_NO_CROSSING; return o; }
     // start: the proposal, else the straight-line root; the closed form when
     // neither exists or when Newton ends outside the crossing window.  A
@@ -689,15 +750,15 @@ __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float
     // accept_cm (that evaluation is Newton's first); otherwise the plain
     // start is used and ML_REJECTED set.
     bool line_ok = true;
-    HelixPt h;
-    float s;
-    float s0 = s_start;
+    HelixT<T> h;
+    T s;
+    T s0 = s_start;
     bool have_first = false;
     int pre = 0;
     if (!isnan(s_start)) {
         helix_at(x, y, cphi, sphi, w, s_start, h);
-        const float f0 = (fmaf(h.x, h.x, h.y * h.y) - R * R) * (0.5f * frcp(R));
-        have_first = fabsf(f0) <= accept_cm && s_start > -BACK_TOL;
+        const T f0 = (fma_(h.x, h.x, h.y * h.y) - R * R) * (T(0.5) * rcp_(R));
+        have_first = fabs(f0) <= accept_cm && s_start > -T(BACK_TOL);
         if (!have_first) {
             o.flags |= ST_ML_REJECTED;
             pre = 1;
@@ -709,23 +770,23 @@ __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float
     }
     bool conv = newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, s0, s, h, o.iters, have_first);
     o.iters += pre;
-    if (!conv || !(s > -BACK_TOL) || fabsf(w * s) > PI_F) {
-        float sc;
+    if (!conv || !(s > -T(BACK_TOL)) || fabs(w * s) > pi_<T>()) {
+        T sc;
         if (!closed_form_cylinder(x, y, cphi, sphi, w, R, sc)) { o.flags |= ST_NO_CROSSING; return o; }
         int it2 = 0;
         conv = newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, sc, s, h, it2);
         o.iters += it2;
-        if (!conv || !(s > -BACK_TOL) || fabsf(w * s) > PI_F) { o.flags |= ST_NEWTON_FAIL; return o; }
+        if (!conv || !(s > -T(BACK_TOL)) || fabs(w * s) > pi_<T>()) { o.flags |= ST_NEWTON_FAIL; return o; }
     }
-    float sinth, costh;
-    sincos_fit(st.p[5], &sinth, &costh);
-    float cot = fdiv(costh, sinth);
-    Jac J;
+    T sinth, costh;
+    sincos_(st.p[5], &sinth, &costh);
+    T cot = div_(costh, sinth);
+    JacT<T> J;
     jacobian_cylinder(x, y, w, kq, s, cot, sinth, h, J);
     st.p[0] = h.x;
     st.p[1] = h.y;
-    st.p[2] = fmaf(s, cot, st.p[2]);
-    st.p[4] = st.p[4] + 2.0f * h.u;
+    st.p[2] = fma_(s, cot, st.p[2]);
+    st.p[4] = st.p[4] + T(2.0) * h.u;
     transport<0>(J, st.c);
     uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
     o.flags |= u;
@@ -735,27 +796,28 @@ __device__ __forceinline__ StepOut step_cylinder(State& st, float R, const float
 }
 
 // Plane z = Z.
-__device__ __forceinline__ StepOut step_plane(State& st, float Z, const float m[3], const float V[6],
-                                              const Params& P, float& chi2) {
+template <typename T>
+__device__ __forceinline__ StepOut step_plane(StateT<T>& st, T Z, const T m[3], const T V[6],
+                                              const Params& P, T& chi2) {
     StepOut o{0u, false, 0};
     if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
-    float sinth, costh;
-    sincos_fit(st.p[5], &sinth, &costh);
-    float tanth = fdiv(sinth, costh);
-    float s = (Z - st.p[2]) * tanth;     // ahead (or at most BACK_TOL behind), within half a turn
-    float kq = -st.q * KAPPA * P.bz;
-    float w = kq * st.p[3];
-    if (!(s > -BACK_TOL) || !(fabsf(w * s) <= PI_F)) { o.flags = ST_NO_CROSSING; return o; }
-    float sphi, cphi;
-    sincos_fit(st.p[4], &sphi, &cphi);
-    HelixPt h;
+    T sinth, costh;
+    sincos_(st.p[5], &sinth, &costh);
+    T tanth = div_(sinth, costh);
+    T s = (Z - st.p[2]) * tanth;     // ahead (or at most T(BACK_TOL) behind), within half a turn
+    T kq = -st.q * T(2.99792458e-3) * P.bz;
+    T w = kq * st.p[3];
+    if (!(s > -T(BACK_TOL)) || !(fabs(w * s) <= pi_<T>())) { o.flags = ST_NO_CROSSING; return o; }
+    T sphi, cphi;
+    sincos_(st.p[4], &sphi, &cphi);
+    HelixT<T> h;
     helix_at(st.p[0], st.p[1], cphi, sphi, w, s, h);
-    Jac J;
+    JacT<T> J;
     jacobian_plane(w, kq, s, tanth, sinth, costh, h, J);
     st.p[0] = h.x;
     st.p[1] = h.y;
     st.p[2] = Z;
-    st.p[4] = st.p[4] + 2.0f * h.u;
+    st.p[4] = st.p[4] + T(2.0) * h.u;
     transport<1>(J, st.c);
     uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
     o.flags |= u;
@@ -768,6 +830,14 @@ __device__ __forceinline__ StepOut step_plane(State& st, float Z, const float m[
 __device__ __forceinline__ float newton_tol(float tol, float R) {
     float ulp = __int_as_float(__float_as_int(fabsf(R)) & 0x7f800000) * 1.1920928955078125e-7f;
     return fmaxf(tol, 2.0f * ulp);
+}
+// FP64 fit: 1e-3 of the requested tolerance (1e-9 cm by default, so that
+// the crossing's own error stays far below the FP32 rounding of the
+// results), but at least 4 ulp(R).
+__device__ __forceinline__ double newton_tol(float tol, double R) {
+    const double ulp = __longlong_as_double(__double_as_longlong(fabs(R)) & 0x7ff0000000000000ll) *
+                       2.220446049250313e-16;
+    return fmax(1e-3 * (double)tol, 4.0 * ulp);
 }
 
 }  // namespace p2r
