@@ -134,6 +134,26 @@ int p2z_propagate_update(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, i
                          const float* layer_z, const float* trk_in, const float* hits,
                          float* trk_out, float* chi2_out, uint32_t* status, void* stream);
 
+/* Transfer-inclusive fits of host-resident tracks (the paper's p2z timing
+ * includes the host-device copies, Section 4).  Same layouts, options and
+ * per-track semantics as p2r_propagate_update / p2z_propagate_update, but
+ * every array, layer_r / layer_z included, is in HOST memory.  The tracks go
+ * in chunks of chunk_tracks (rounded up to whole blocks; 0 = 131072): each
+ * chunk is copied in, fitted and copied back on one of three internal
+ * streams, so the copies of one chunk overlap the fit of another.  The copies
+ * overlap only from pinned host memory (hipHostMalloc); pageable memory
+ * works but serialises them.  The pipeline is ordered after the work already
+ * queued on `stream`, and `stream` waits for its end; the call returns
+ * without waiting, and the host buffers must stay untouched until `stream`
+ * reaches that point.  Staging buffers (three chunks) live in the context:
+ * calls on one context must not overlap.  Not with an MLP. */
+int p2r_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int32_t n_layers,
+                              const float* layer_r, const float* trk_in, const float* hits, float* trk_out,
+                              float* chi2_out, uint32_t* status, int32_t chunk_tracks, void* stream);
+int p2z_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int32_t n_layers,
+                              const float* layer_z, const float* trk_in, const float* hits, float* trk_out,
+                              float* chi2_out, uint32_t* status, int32_t chunk_tracks, void* stream);
+
 /* Ragged batched fit (paper Section 2's per-track layer loop with per-track
  * layer lists): every track has its own ordered list of surfaces (CSR),
  * each a cylinder (surf_type 0, surf_val = radius) or a plane (surf_type 1,

@@ -65,6 +65,8 @@ def library():
         for f in (L.p2r_propagate_update, L.p2z_propagate_update):
             f.argtypes = [vp, C.POINTER(Opts), i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.p2r_autotune.argtypes = [vp, C.c_int, i32, i32, vp]
+        for f in (L.p2r_propagate_update_host, L.p2z_propagate_update_host):
+            f.argtypes = [vp, C.POINTER(Opts), i32, i32, vp, vp, vp, vp, vp, vp, i32, vp]
         L.p2r_set_variant.argtypes = [vp, C.c_int, C.c_char_p]
         L.p2r_variant_at.argtypes = [C.c_int, C.c_int]
         L.p2r_variant_at.restype = C.c_char_p
@@ -184,6 +186,26 @@ class Context:
         _check(library().p2z_propagate_update(self._h, C.byref(opts), n_tracks, layer_z.numel(), _ptr(layer_z),
                                               _ptr(trk_in), _ptr(hits), _ptr(trk_out), _ptr(chi2),
                                               _ptr(status), _stream(stream)))
+        return trk_out, chi2, status
+
+    def propagate_update_host(self, which, n_tracks, layer, trk_in, hits, out=None, opts=None, stream=None,
+                              chunk_tracks=0, **kw):
+        """Transfer-inclusive fit of host tensors (which 0 p2r, 1 p2z); returns host (trk_out, chi2, status).
+
+        Pass pinned tensors (pin_memory()) for the copies to overlap; the
+        results are complete once `stream` (torch's current by default) has
+        reached the end of the call."""
+        opts = opts or default_opts(**kw)
+        for t in (layer, trk_in, hits):
+            if t.is_cuda:
+                raise ValueError("the host pipeline takes host tensors")
+        if out is None:
+            out = (torch.empty_like(trk_in).pin_memory(), torch.empty(n_tracks, dtype=torch.float32).pin_memory(),
+                   torch.empty(n_tracks, dtype=torch.int32).pin_memory())
+        trk_out, chi2, status = out
+        fn = library().p2r_propagate_update_host if which == 0 else library().p2z_propagate_update_host
+        _check(fn(self._h, C.byref(opts), n_tracks, layer.numel(), _ptr(layer), _ptr(trk_in), _ptr(hits),
+                  _ptr(trk_out), _ptr(chi2), _ptr(status), int(chunk_tracks), _stream(stream)))
         return trk_out, chi2, status
 
     def fit_tracks_batched(self, offsets, surf_type, surf_val, hit_pos, hit_cov, par_in, cov_in, q,

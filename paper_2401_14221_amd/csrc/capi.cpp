@@ -90,6 +90,16 @@ struct p2r_ctx {
     hipGraphExec_t exec = nullptr;
     RaggedKey key;
     bool have_graph = false;
+    // host pipeline (p2r/p2z_propagate_update_host): streams, events and
+    // per-stream staging buffers, created on first use and grown when needed
+    static constexpr int NPIPE = 3;
+    hipStream_t pipe_s[NPIPE] = {};
+    hipEvent_t pipe_done[NPIPE] = {};
+    hipEvent_t pipe_start = nullptr;
+    void* pipe_buf[NPIPE] = {};
+    size_t pipe_bytes = 0;
+    float* pipe_surf = nullptr;
+    int32_t pipe_surf_cap = 0;
 };
 
 struct p2r_mlp {
@@ -256,6 +266,14 @@ void p2r_ctx_destroy(p2r_ctx* ctx) {
     DeviceGuard g(ctx->device);
     if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    for (int k = 0; k < p2r_ctx::NPIPE; ++k) {
+        if (ctx->pipe_s[k]) (void)hipStreamSynchronize(ctx->pipe_s[k]);
+        if (ctx->pipe_done[k]) (void)hipEventDestroy(ctx->pipe_done[k]);
+        if (ctx->pipe_s[k]) (void)hipStreamDestroy(ctx->pipe_s[k]);
+        if (ctx->pipe_buf[k]) (void)hipFree(ctx->pipe_buf[k]);
+    }
+    if (ctx->pipe_start) (void)hipEventDestroy(ctx->pipe_start);
+    if (ctx->pipe_surf) (void)hipFree(ctx->pipe_surf);
     void* bufs[] = {ctx->rag_hist, ctx->rag_base, ctx->rag_work, ctx->rag_perm, ctx->rag_keys, ctx->rag_blk_off,
                     ctx->rag_packed};
     for (void* b : bufs)
@@ -341,6 +359,135 @@ int p2z_propagate_update(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, i
                          float* chi2_out, uint32_t* status, void* stream) {
     return propagate_common(1, ctx, opts, n_tracks, n_layers, layer_z, trk_in, hits, trk_out, chi2_out, status,
                             stream);
+}
+
+// Host-to-host fit in chunks on NPIPE streams: chunk c is copied in, fitted
+// and copied back on stream c % NPIPE, into that stream's staging buffers,
+// so the copies of one chunk overlap the fit of another; stream order makes
+// a staging buffer's reuse wait for its previous chunk.  The pipeline starts
+// after the work already queued on `stream` and `stream` waits for its end.
+static int propagate_host(int which, p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int32_t n_layers,
+                          const float* surf, const float* trk_in, const float* hits, float* trk_out,
+                          float* chi2_out, uint32_t* status, int32_t chunk_tracks, void* stream) {
+    if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    if (opts->mlp) return fail(P2R_EINVAL, "the host pipeline runs the plain fit (no mlp)");
+    if (n_tracks < 0 || n_layers < 0) return fail(P2R_EINVAL, "negative size (n_tracks %d, n_layers %d)", n_tracks, n_layers);
+    if (n_layers > 4096) return fail(P2R_EINVAL, "n_layers %d above 4096", n_layers);
+    if (chunk_tracks < 0) return fail(P2R_EINVAL, "chunk_tracks must be >= 0");
+    if (which == 1 && opts->width != 0 && opts->width != 64)
+        return fail(P2R_ELAYOUT, "p2z layout width is 64 (got %d)", opts->width);
+    if (n_tracks == 0) return P2R_OK;
+    if (!trk_in || !trk_out || !chi2_out || !status || (n_layers > 0 && (!hits || !surf)))
+        return fail(P2R_EINVAL, "NULL buffer");
+    const p2r::Variant* v = nullptr;
+    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v, false, opts->fp64 != 0);
+    if (rc) return rc;
+    const int W = v->width;
+    const int64_t nb = ((int64_t)n_tracks + W - 1) / W;
+    int64_t cb = chunk_tracks > 0 ? ((int64_t)chunk_tracks + W - 1) / W : (131072 + W - 1) / W;   // blocks per chunk
+    if (cb > nb) cb = nb;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e;
+    if (!ctx->pipe_start) {
+        for (int k = 0; k < p2r_ctx::NPIPE; ++k) {
+            if ((e = hipStreamCreateWithFlags(&ctx->pipe_s[k], hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreateWithFlags");
+            if ((e = hipEventCreateWithFlags(&ctx->pipe_done[k], hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "hipEventCreateWithFlags");
+        }
+        if ((e = hipEventCreateWithFlags(&ctx->pipe_start, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    // staging per stream: tracks in and out [cb][28][W], hits [cb][L][9][W]
+    // (p2z: [L][cb][9][64]), chi2 and status [cb W]
+    const size_t trk_f = (size_t)cb * 28 * W, hit_f = (size_t)cb * n_layers * 9 * W, trk_n = (size_t)cb * W;
+    const size_t bytes = sizeof(float) * (2 * trk_f + hit_f + 2 * trk_n);
+    hipStream_t us = (hipStream_t)stream;
+    if (bytes > ctx->pipe_bytes) {
+        for (int k = 0; k < p2r_ctx::NPIPE; ++k) {
+            (void)hipStreamSynchronize(ctx->pipe_s[k]);
+            if (ctx->pipe_buf[k]) (void)hipFree(ctx->pipe_buf[k]);
+            ctx->pipe_buf[k] = nullptr;
+        }
+        ctx->pipe_bytes = 0;
+        for (int k = 0; k < p2r_ctx::NPIPE; ++k)
+            if ((e = hipMalloc(&ctx->pipe_buf[k], bytes)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        ctx->pipe_bytes = bytes;
+    }
+    if (n_layers > ctx->pipe_surf_cap) {
+        if (ctx->pipe_surf) (void)hipFree(ctx->pipe_surf);
+        ctx->pipe_surf = nullptr;
+        ctx->pipe_surf_cap = 0;
+        if ((e = hipMalloc(&ctx->pipe_surf, sizeof(float) * n_layers)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        ctx->pipe_surf_cap = n_layers;
+    }
+    // the surface table, then the pipeline, after the caller's queued work
+    if (n_layers > 0 &&
+        (e = hipMemcpyAsync(ctx->pipe_surf, surf, sizeof(float) * n_layers, hipMemcpyHostToDevice, us)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipEventRecord(ctx->pipe_start, us)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int k = 0; k < p2r_ctx::NPIPE; ++k)
+        if ((e = hipStreamWaitEvent(ctx->pipe_s[k], ctx->pipe_start, 0)) != hipSuccess)
+            return hip_fail(e, "hipStreamWaitEvent");
+    const p2r::Params P = params_of(opts);
+    const size_t blk_trk = (size_t)28 * W;               // floats per track block
+    const size_t blk_hit = (size_t)n_layers * 9 * W;      // floats of hits per block (all layers)
+    int64_t chunk = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += cb, ++chunk) {
+        const int k = (int)(chunk % p2r_ctx::NPIPE);
+        hipStream_t s = ctx->pipe_s[k];
+        const int64_t b1 = std::min(nb, b0 + cb);
+        const int64_t nbc = b1 - b0;
+        const int64_t t0 = b0 * W;
+        const int32_t nc = (int32_t)(std::min<int64_t>(n_tracks, b1 * W) - t0);
+        float* st_trk = static_cast<float*>(ctx->pipe_buf[k]);
+        float* st_out = st_trk + trk_f;
+        float* st_hit = st_out + trk_f;
+        float* st_chi2 = st_hit + hit_f;
+        uint32_t* st_status = reinterpret_cast<uint32_t*>(st_chi2 + trk_n);
+        if ((e = hipMemcpyAsync(st_trk, trk_in + b0 * blk_trk, sizeof(float) * nbc * blk_trk, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync");
+        if (n_layers > 0) {
+            if (which == 0) {
+                e = hipMemcpyAsync(st_hit, hits + b0 * blk_hit, sizeof(float) * nbc * blk_hit, hipMemcpyHostToDevice, s);
+            } else {
+                // layer-outer hits: one row of nbc blocks per layer
+                const size_t row = sizeof(float) * 9 * W;
+                e = hipMemcpy2DAsync(st_hit, row * nbc, hits + b0 * 9 * W, row * nb, row * nbc, n_layers,
+                                     hipMemcpyHostToDevice, s);
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (hits)");
+        }
+        p2r::FitLaunch a{nc, n_layers, ctx->pipe_surf, st_trk, st_hit, st_out, st_chi2, st_status, nullptr,
+                         opts->helix_evals};
+        if ((e = p2r::launch_fit(*v, a, P, s)) != hipSuccess) return hip_fail(e, "kernel launch");
+        if ((e = hipMemcpyAsync(trk_out + b0 * blk_trk, st_out, sizeof(float) * nbc * blk_trk, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(chi2_out + t0, st_chi2, sizeof(float) * nc, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(status + t0, st_status, sizeof(uint32_t) * nc, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync (results)");
+    }
+    for (int k = 0; k < p2r_ctx::NPIPE; ++k) {
+        if ((e = hipEventRecord(ctx->pipe_done[k], ctx->pipe_s[k])) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = hipStreamWaitEvent(us, ctx->pipe_done[k], 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    }
+    return P2R_OK;
+}
+
+int p2r_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int32_t n_layers,
+                              const float* layer_r, const float* trk_in, const float* hits, float* trk_out,
+                              float* chi2_out, uint32_t* status, int32_t chunk_tracks, void* stream) {
+    return propagate_host(0, ctx, opts, n_tracks, n_layers, layer_r, trk_in, hits, trk_out, chi2_out, status,
+                          chunk_tracks, stream);
+}
+
+int p2z_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int32_t n_layers,
+                              const float* layer_z, const float* trk_in, const float* hits, float* trk_out,
+                              float* chi2_out, uint32_t* status, int32_t chunk_tracks, void* stream) {
+    return propagate_host(1, ctx, opts, n_tracks, n_layers, layer_z, trk_in, hits, trk_out, chi2_out, status,
+                          chunk_tracks, stream);
 }
 
 int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits, int32_t max_surfaces,

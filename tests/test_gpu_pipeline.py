@@ -1,0 +1,88 @@
+"""Transfer-inclusive host pipeline (chunks on three streams) against the
+device-resident fit: the same kernels on the same data, so the results are
+bit-for-bit identical whatever the chunking."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2401_14221_amd as p2r
+from synth import events as ev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = p2r.Context(0)
+    yield c
+    c.close()
+
+
+def _device(ctx, which, d, W):
+    if which == 0:
+        trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device="cuda")
+        hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device="cuda")
+        surf = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
+        r = ctx.p2r_propagate_update(d["par"].shape[0], surf, trk, hits, width=W)
+    else:
+        trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64, device="cuda")
+        hits = p2r.pack_hits_p2z(d["hits"], d["hitcov"], device="cuda")
+        surf = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
+        r = ctx.p2z_propagate_update(d["par"].shape[0], surf, trk, hits)
+    torch.cuda.synchronize()
+    return [t.cpu() for t in r]
+
+
+def _host(ctx, which, d, W, chunk):
+    if which == 0:
+        trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W).pin_memory()
+        hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W).pin_memory()
+    else:
+        trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64).pin_memory()
+        hits = p2r.pack_hits_p2z(d["hits"], d["hitcov"]).pin_memory()
+    surf = torch.as_tensor(d["surf"], dtype=torch.float32)
+    s = torch.cuda.Stream()
+    r = ctx.propagate_update_host(which, d["par"].shape[0], surf, trk, hits, chunk_tracks=chunk, stream=s,
+                                  width=W if which == 0 else 0)
+    s.synchronize()
+    return [t.clone() for t in r]
+
+
+@pytest.mark.parametrize("which,W,n,chunk", [(1, 64, 5000, 1000), (1, 64, 4097, 0), (1, 64, 64, 64),
+                                             (0, 64, 5000, 1000), (0, 128, 3001, 700), (0, 256, 2000, 256)])
+def test_host_pipeline_equals_device_fit(ctx, which, W, n, chunk):
+    if which == 0:
+        d = ev.make_barrel_event(ev.P2R_THROUGHPUT.with_(seed=81), n_tracks=n)
+    else:
+        d = ev.make_disk_event(ev.P2Z_THROUGHPUT.with_(seed=82), n_tracks=n)
+    a = _device(ctx, which, d, W)
+    b = _host(ctx, which, d, W, chunk)
+    nb = (n + W - 1) // W
+    # whole blocks of the record array (tail lanes are never written by either path)
+    pa, ca, qa = p2r.unpack_tracks(a[0], n)
+    pb, cb, qb = p2r.unpack_tracks(b[0], n)
+    assert torch.equal(pa, pb) and torch.equal(ca, cb) and torch.equal(qa, qb)
+    assert torch.equal(a[1], b[1])
+    assert torch.equal(a[2], b[2])
+    assert b[0].shape[0] == nb
+
+
+def test_host_pipeline_edge_cases(ctx):
+    d = ev.make_disk_event(ev.P2Z_THROUGHPUT.with_(seed=83), n_tracks=100)
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64).pin_memory()
+    hits = p2r.pack_hits_p2z(d["hits"], d["hitcov"]).pin_memory()
+    surf = torch.as_tensor(d["surf"], dtype=torch.float32)
+    # no tracks: nothing to do
+    ctx.propagate_update_host(1, 0, surf, trk, hits)
+    with pytest.raises(ValueError):
+        ctx.propagate_update_host(1, 100, surf.cuda(), trk, hits)
+    with pytest.raises(p2r.P2RError):
+        ctx.propagate_update_host(1, 100, surf, trk, hits, chunk_tracks=-5)
+    m = p2r.Mlp(ctx)
+    with pytest.raises(p2r.P2RError):
+        ctx.propagate_update_host(0, 100, surf, trk, hits, mlp=m.handle.value)
+    # pageable host memory works too (copies serialise)
+    r = ctx.propagate_update_host(1, 100, surf, trk.clone(), hits.clone(), chunk_tracks=64)
+    torch.cuda.synchronize()
+    a = _device(ctx, 1, d, 64)
+    assert torch.equal(a[1], r[1])
