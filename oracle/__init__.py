@@ -52,7 +52,9 @@ def lib():
         L.orc_propagate.restype = C.c_int
         L.orc_update.argtypes = [dp, dp, dp, dp, C.c_int, C.c_double, dp, dp, dp]
         L.orc_update.restype = C.c_uint32
-        L.orc_fit.argtypes = [C.c_int64] + [C.c_void_p] * 8 + [C.c_double, C.c_double, C.c_int, C.c_int] \
+        L.orc_update_2d.argtypes = [dp, dp, dp, dp, C.c_double, dp, dp, dp]
+        L.orc_update_2d.restype = C.c_uint32
+        L.orc_fit.argtypes = [C.c_int64] + [C.c_void_p] * 8 + [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int] \
             + [C.c_void_p] * 8
         L.orc_fit.restype = None
         L.orc_disk_sign.argtypes = [C.c_double]
@@ -105,10 +107,20 @@ def update(p, C6, m, V21, form=0, chi2_cut=0.0):
     return int(st), po, Co.reshape(6, 6), float(c2[0])
 
 
+def update_2d(p, C6, m, V21, chi2_cut=0.0):
+    """Update in the hit's (r-phi, z) frame on a cylinder: (status, p+, C+ 6x6, chi2)."""
+    p, C6, m, V21 = _f64(p, (6,)), _f64(C6, (36,)), _f64(m, (3,)), _f64(V21, (6,))
+    po, Co, c2 = np.zeros(6), np.zeros(36), np.zeros(1)
+    st = lib().orc_update_2d(_dp(p), _dp(C6), _dp(m), _dp(V21), float(chi2_cut), _dp(po), _dp(Co), _dp(c2))
+    return int(st), po, Co.reshape(6, 6), float(c2[0])
+
+
 # ------------------------------------------------------------------ batches
 def fit(par, cov, q, offsets, stype, sval, hits, hitcov, bz=3.8, chi2_cut=0.0, form=0,
-        nthreads=0, layers=False):
-    """Per-track fit over CSR surface lists; returns a dict of outputs."""
+        nthreads=0, layers=False, update_2d=False):
+    """Per-track fit over CSR surface lists; returns a dict of outputs.
+
+    update_2d: cylinders take the update in the hit's (r-phi, z) frame."""
     par, cov, q = _f64(par), _f64(cov), _f64(q)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     stype = np.ascontiguousarray(stype, dtype=np.uint8)
@@ -126,7 +138,7 @@ def fit(par, cov, q, offsets, stype, sval, hits, hitcov, bz=3.8, chi2_cut=0.0, f
     lp = [vp(out[k]) if layers else None for k in ("lay_par", "lay_cov", "lay_chi2")] if layers \
         else [None, None, None]
     lib().orc_fit(n, vp(par), vp(cov), vp(q), vp(offsets), vp(stype), vp(sval), vp(hits), vp(hitcov),
-                  float(bz), float(chi2_cut), int(form), int(nthreads),
+                  float(bz), float(chi2_cut), int(form), int(bool(update_2d)), int(nthreads),
                   vp(out["par"]), vp(out["cov"]), vp(out["chi2"]), vp(out["nused"]), vp(out["status"]),
                   *lp)
     return out

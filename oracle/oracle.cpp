@@ -345,12 +345,79 @@ uint32_t kalman_update(const double p[6], const double C[36], const double m[3],
     return 0;
 }
 
+// ------------------------------------------ O6': update in the hit's frame
+// On a cylinder only the two coordinates along the surface are measured:
+// with (c, s) the direction of the hit in the transverse plane,
+//   u = -s x + c y   (the r-phi coordinate, u_hit = 0)   and   z,
+// so H (2x6) = [[-s, c, 0, 0, 0, 0], [0, 0, 1, 0, 0, 0]], the measurement
+// covariance is V2 = R V R^T with R = [[-s, c, 0], [0, 0, 1]], and the
+// update is the linear Kalman update with that H: S = H C' H^T + V2,
+// K = C' H^T S^-1, p+ = p' + K r, Joseph C+ = (I-KH) C' (I-KH)^T + K V2 K^T,
+// chi2 = r^T S^-1 r (two degrees of freedom).
+uint32_t kalman_update_2d(const double p[6], const double C[36], const double m[3], const double V21[6],
+                          double chi2_cut, double pout[6], double Cout[36], double* chi2) {
+    const double rh = std::hypot(m[0], m[1]);
+    if (!(rh > 0.0)) return ST_S_NOT_PD;
+    const double c = m[0] / rh, s = m[1] / rh;
+    double H[12] = {0};
+    H[0] = -s; H[1] = c; H[6 + 2] = 1.0;
+    double V[9];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) {
+        int a = i > j ? i : j, b = i > j ? j : i;
+        V[i * 3 + j] = V21[a * (a + 1) / 2 + b];
+    }
+    const double R[6] = {-s, c, 0.0, 0.0, 0.0, 1.0};
+    double RV[6], Rt[6], V2[4];
+    matmul(R, V, RV, 2, 3, 3);
+    transpose(R, Rt, 2, 3);
+    matmul(RV, Rt, V2, 2, 3, 2);
+    double Ht[12], CHt[12], S[4];
+    transpose(H, Ht, 2, 6);
+    matmul(C, Ht, CHt, 6, 6, 2);
+    matmul(H, CHt, S, 2, 6, 2);
+    for (int i = 0; i < 4; ++i) S[i] += V2[i];
+    // 2x2 Cholesky with the same pivot rule as the 3x3 one
+    const double l00sq = S[0];
+    if (!(l00sq > PD_TAU * S[0]) || !std::isfinite(l00sq)) return ST_S_NOT_PD;
+    const double d1 = S[3] - S[2] * S[2] / S[0];
+    if (!(d1 > PD_TAU * S[3]) || !std::isfinite(d1)) return ST_S_NOT_PD;
+    const double det = S[0] * S[3] - S[1] * S[2];
+    const double Sinv[4] = {S[3] / det, -S[1] / det, -S[2] / det, S[0] / det};
+    double Hp[2], r[2];
+    matmul(H, p, Hp, 2, 6, 1);
+    const double mloc[2] = {-s * m[0] + c * m[1], m[2]};
+    for (int i = 0; i < 2; ++i) r[i] = mloc[i] - Hp[i];
+    double c2 = 0.0;
+    for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) c2 += r[i] * Sinv[i * 2 + j] * r[j];
+    if (chi2_cut > 0.0 && c2 > chi2_cut) return ST_CHI2_CUT;
+    double K[12];
+    matmul(CHt, Sinv, K, 6, 2, 2);
+    for (int i = 0; i < 6; ++i) pout[i] = p[i] + K[i * 2] * r[0] + K[i * 2 + 1] * r[1];
+    pout[4] = wrap_phi(pout[4]);
+    double KH[36], A[36], AC[36], At[36], ACAt[36], KV[12], Kt[12], KVKt[36];
+    matmul(K, H, KH, 6, 2, 6);
+    for (int i = 0; i < 36; ++i) A[i] = ((i / 6) == (i % 6) ? 1.0 : 0.0) - KH[i];
+    matmul(A, C, AC, 6, 6, 6);
+    transpose(A, At, 6, 6);
+    matmul(AC, At, ACAt, 6, 6, 6);
+    matmul(K, V2, KV, 6, 2, 2);
+    transpose(K, Kt, 6, 2);
+    matmul(KV, Kt, KVKt, 6, 2, 6);
+    for (int i = 0; i < 36; ++i) Cout[i] = ACAt[i] + KVKt[i];
+    for (int i = 0; i < 6; ++i) for (int j = 0; j < i; ++j) {
+        double a = 0.5 * (Cout[i * 6 + j] + Cout[j * 6 + i]);
+        Cout[i * 6 + j] = Cout[j * 6 + i] = a;
+    }
+    *chi2 = c2;
+    return 0;
+}
+
 // ------------------------------------------------- O7: the per-track fit
 struct FitArgs {
     const double* par; const double* cov; const double* q;
     const int64_t* offsets; const uint8_t* stype; const double* sval;
     const double* hits; const double* hitcov;
-    double bz, chi2_cut; int form;
+    double bz, chi2_cut; int form; int update_2d;
     double* par_out; double* cov_out; double* chi2_out; int32_t* nused_out; uint32_t* status_out;
     double* lay_par; double* lay_cov; double* lay_chi2;   // nullable per-surface dumps
 };
@@ -395,7 +462,9 @@ void fit_one(const FitArgs& a, int64_t t) {
                         Cp[i * 6 + j] = Cp[j * 6 + i] = v;
                     }
                     double pu[6], Cu[36], c2 = 0.0;
-                    uint32_t u = kalman_update(pp, Cp, m, a.hitcov + h * 6, a.form, a.chi2_cut, pu, Cu, &c2);
+                    uint32_t u = (a.update_2d && a.stype[h] == 0)
+                                     ? kalman_update_2d(pp, Cp, m, a.hitcov + h * 6, a.chi2_cut, pu, Cu, &c2)
+                                     : kalman_update(pp, Cp, m, a.hitcov + h * 6, a.form, a.chi2_cut, pu, Cu, &c2);
                     if (u == 0) {
                         std::memcpy(p, pu, sizeof p);
                         std::memcpy(C, Cu, sizeof C);
@@ -450,20 +519,27 @@ uint32_t orc_update(const double p[6], const double C36[36], const double m[3], 
     return kalman_update(p, C36, m, V21, form, chi2_cut, pout, Cout36, chi2);
 }
 
+// Update O6' in the hit's (r-phi, z) frame on a cylinder.
+uint32_t orc_update_2d(const double p[6], const double C36[36], const double m[3], const double V21[6],
+                       double chi2_cut, double pout[6], double Cout36[36], double* chi2) {
+    return kalman_update_2d(p, C36, m, V21, chi2_cut, pout, Cout36, chi2);
+}
+
 // The per-track fit over a CSR list of surfaces.
 //   par [n][6], cov [n][21], q [n]; offsets [n+1]; per surface h:
 //   stype[h] (0 cylinder, 1 plane), sval[h] (radius or signed z),
 //   hits [H][3], hitcov [H][6].  Outputs par_out [n][6], cov_out [n][21],
 //   chi2_out [n], nused_out [n], status_out [n]; optional per-surface
 //   states after each surface (lay_par [H][6], lay_cov [H][21], lay_chi2 [H]).
+//   update_2d: cylinders take the update in the hit's (r-phi, z) frame (O6').
 //   nthreads <= 0 means hardware concurrency.
 void orc_fit(int64_t n, const double* par, const double* cov, const double* q,
              const int64_t* offsets, const uint8_t* stype, const double* sval,
              const double* hits, const double* hitcov, double bz, double chi2_cut, int form,
-             int nthreads, double* par_out, double* cov_out, double* chi2_out,
+             int update_2d, int nthreads, double* par_out, double* cov_out, double* chi2_out,
              int32_t* nused_out, uint32_t* status_out,
              double* lay_par, double* lay_cov, double* lay_chi2) {
-    FitArgs a{par, cov, q, offsets, stype, sval, hits, hitcov, bz, chi2_cut, form,
+    FitArgs a{par, cov, q, offsets, stype, sval, hits, hitcov, bz, chi2_cut, form, update_2d,
               par_out, cov_out, chi2_out, nused_out, status_out, lay_par, lay_cov, lay_chi2};
     int nt = nthreads > 0 ? nthreads : (int)std::max(1u, std::thread::hardware_concurrency());
     if (nt > n) nt = (int)std::max<int64_t>(1, n);
