@@ -213,6 +213,16 @@ def main():
         ms_cf, _ = timed(step_cf, args.steps, args.warmup, stream)
         res["closed_form_start"] = {"ms_per_step": ms_cf, "value": tl / (ms_cf * 1e-3), "unit": UNIT}
         log(f"p2r closed-form start: {ms_cf:.3f} ms/step")
+        # the update in the hit's (r-phi, z) frame (two measured coordinates)
+        opts_2d = p2r._lib.default_opts(width=W, update_2d=1)
+
+        def step_2d():
+            ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts_2d, stream=stream)
+
+        ms_2d, _ = timed(step_2d, args.steps, args.warmup, stream)
+        res["update_2d"] = {"ms_per_step": ms_2d, "value": tl / (ms_2d * 1e-3), "unit": UNIT,
+                            "note": "Kalman update in the hit's (r-phi, z) frame, chi2 with 2 dof"}
+        log(f"p2r hit-frame update: {ms_2d:.3f} ms/step")
         # every step in FP64 (same inputs, results rounded to FP32)
         opts_64 = p2r._lib.default_opts(width=W, fp64=1)
 

@@ -96,6 +96,11 @@ typedef struct {
                                 FP32 inputs, results rounded to FP32 (a precision reference; the
                                 Newton tolerance becomes 1e-3 newton_tol_cm, the PD test the
                                 FP64 one; not with an MLP) */
+    int32_t update_2d;       /* cylinders: 0 = update with the 3D hit in global x, y, z (default);
+                                1 = update in the hit's (r-phi, z) frame, 2 measured coordinates
+                                (u = -s x + c y, z with (c, s) the hit's azimuth, V2 = R V R^T),
+                                chi2 with 2 degrees of freedom.  Planes are unaffected: there the
+                                3D update already equals the 2D one (the z residual is 0). */
 } p2r_opts;
 
 void p2r_opts_default(p2r_opts* o);

@@ -33,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("bz_tesla", C.c_float), ("newton_tol_cm", C.c_float), ("newton_max_iter", C.c_int32),
                 ("chi2_cut", C.c_float), ("fp64_fallback", C.c_int32), ("width", C.c_int32),
                 ("mlp", C.c_void_p), ("use_graph", C.c_int32), ("helix_evals", C.c_void_p),
-                ("cyl_start", C.c_int32), ("fp64", C.c_int32)]
+                ("cyl_start", C.c_int32), ("fp64", C.c_int32), ("update_2d", C.c_int32)]
 
 
 _lib = None

@@ -85,7 +85,7 @@ struct p2r_ctx {
     float* rag_packed = nullptr;
     int32_t rag_n_cap = 0, rag_nkeys_cap = 0;
     int64_t rag_packed_cap = 0;
-    int rag_blocks_per_cu[3] = {0, 0, 0};   // FP32 fit, FP32 fit at 4 waves, FP64 fit
+    std::map<const void*, int> rag_blocks_per_cu;   // resident workgroups per CU of each persistent fit
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     RaggedKey key;
@@ -119,20 +119,25 @@ const p2r::Variant* find_variant(int which, const std::string& name) {
 int default_variant(int which) {
     const auto& vs = p2r::variants();
     for (size_t i = 0; i < vs.size(); ++i)
-        if (vs[i].which == which && !vs[i].learned && !vs[i].fp64) return (int)i;
+        if (vs[i].which == which && !vs[i].learned && !vs[i].fp64 && !vs[i].upd2d) return (int)i;
     return -1;
 }
 
 int variant_for(p2r_ctx* ctx, int which, int width, const p2r::Variant** out, bool learned = false,
-                bool fp64 = false) {
+                bool fp64 = false, bool upd2d = false) {
     const auto& vs = p2r::variants();
     int idx = ctx->chosen[which] >= 0 ? ctx->chosen[which] : default_variant(which);
     if (idx < 0) return fail(P2R_ENOTUNED, "no kernel variant compiled for which=%d", which);
-    if (fp64) {
+    if (which == 1) upd2d = false;      // planes: the 3D update already is the 2D one
+    if (fp64 || upd2d) {
         const int w = width != 0 ? width : vs[idx].width;
         for (const auto& v : vs)
-            if (v.which == which && v.fp64 && v.width == w) { *out = &v; return P2R_OK; }
-        return fail(P2R_ELAYOUT, "no FP64 kernel for width %d", w);
+            if (v.which == which && !v.learned && v.fp64 == fp64 && v.upd2d == upd2d && v.width == w) {
+                *out = &v;
+                return P2R_OK;
+            }
+        return fail(P2R_ELAYOUT, "no %s%skernel for width %d", fp64 ? "FP64 " : "",
+                    upd2d ? "hit-frame-update " : "", w);
     }
     if (learned) {
         const int w = width != 0 ? width : vs[idx].width;
@@ -144,7 +149,10 @@ int variant_for(p2r_ctx* ctx, int which, int width, const p2r::Variant** out, bo
         // first variant of this width (prefer the tuned occupancy/unroll when it matches)
         idx = -1;
         for (size_t i = 0; i < vs.size(); ++i)
-            if (vs[i].which == which && vs[i].width == width && !vs[i].learned && !vs[i].fp64) { idx = (int)i; break; }
+            if (vs[i].which == which && vs[i].width == width && !vs[i].learned && !vs[i].fp64 && !vs[i].upd2d) {
+                idx = (int)i;
+                break;
+            }
         if (idx < 0) return fail(P2R_ELAYOUT, "layout width %d not supported (32, 64, 128, 256 for p2r; 64 for p2z)", width);
     }
     (void)0;
@@ -172,6 +180,8 @@ int check_opts(const p2r_opts* o) {
     if (o->fp64_fallback < 0 || o->fp64_fallback > 3) return fail(P2R_EINVAL, "fp64_fallback must be 0, 1, 2 or 3");
     if (o->cyl_start < 0 || o->cyl_start > 1) return fail(P2R_EINVAL, "cyl_start must be 0 or 1");
     if (o->fp64 < 0 || o->fp64 > 1) return fail(P2R_EINVAL, "fp64 must be 0 or 1");
+    if (o->update_2d < 0 || o->update_2d > 1) return fail(P2R_EINVAL, "update_2d must be 0 or 1");
+    if (o->update_2d && o->mlp) return fail(P2R_EINVAL, "the learned start uses the 3D update (update_2d = 1 with an mlp)");
     if (o->fp64 && o->mlp) return fail(P2R_EINVAL, "the learned start runs in FP32 only (fp64 = 1 with an mlp)");
     return P2R_OK;
 }
@@ -237,6 +247,7 @@ void p2r_opts_default(p2r_opts* o) {
     o->helix_evals = nullptr;
     o->cyl_start = 0;
     o->fp64 = 0;
+    o->update_2d = 0;
 }
 
 int p2r_ctx_create(p2r_ctx** out, int device, const char* tune_cache_path) {
@@ -294,7 +305,7 @@ int p2r_layout_width(p2r_ctx* ctx, int which, int32_t* W_out) {
 const char* p2r_variant_at(int which, int i) {
     int k = 0;
     for (const auto& v : p2r::variants())
-        if (v.which == which && !v.learned && !v.fp64 && k++ == i) return v.name;
+        if (v.which == which && !v.learned && !v.fp64 && !v.upd2d && k++ == i) return v.name;
     return nullptr;
 }
 
@@ -303,7 +314,8 @@ int p2r_set_variant(p2r_ctx* ctx, int which, const char* name) {
     if (which < 0 || which > 2) return fail(P2R_EINVAL, "which must be 0 (p2r), 1 (p2z) or 2 (ragged)");
     if (!name) return fail(P2R_EINVAL, "name is NULL");
     const p2r::Variant* v = find_variant(which, name);
-    if (!v || v->learned || v->fp64) return fail(P2R_ENOTUNED, "no plain kernel variant named '%s' for which=%d", name, which);
+    if (!v || v->learned || v->fp64 || v->upd2d)
+        return fail(P2R_ENOTUNED, "no plain kernel variant named '%s' for which=%d", name, which);
     ctx->chosen[which] = (int)(v - p2r::variants().data());
     return P2R_OK;
 }
@@ -336,7 +348,8 @@ static int propagate_common(int which, p2r_ctx* ctx, const p2r_opts* opts, int32
     const p2r::Variant* v = nullptr;
     const p2r_mlp* mlp = static_cast<const p2r_mlp*>(opts->mlp);
     if (mlp && mlp->device != ctx->device) return fail(P2R_EINVAL, "mlp lives on device %d, context on %d", mlp->device, ctx->device);
-    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v, mlp != nullptr, opts->fp64 != 0);
+    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v, mlp != nullptr, opts->fp64 != 0,
+                     opts->update_2d != 0);
     if (rc) return rc;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
@@ -382,7 +395,7 @@ static int propagate_host(int which, p2r_ctx* ctx, const p2r_opts* opts, int32_t
     if (!trk_in || !trk_out || !chi2_out || !status || (n_layers > 0 && (!hits || !surf)))
         return fail(P2R_EINVAL, "NULL buffer");
     const p2r::Variant* v = nullptr;
-    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v, false, opts->fp64 != 0);
+    rc = variant_for(ctx, which, which == 0 ? opts->width : 0, &v, false, opts->fp64 != 0, opts->update_2d != 0);
     if (rc) return rc;
     const int W = v->width;
     const int64_t nb = ((int64_t)n_tracks + W - 1) / W;
@@ -515,7 +528,7 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     for (const void* p : a4)
         if (p && !aligned(p, 4)) return fail(P2R_ELAYOUT, "buffer not 4-byte aligned");
     const p2r::Variant* v = nullptr;
-    rc = variant_for(ctx, 2, 0, &v, false, opts->fp64 != 0);
+    rc = variant_for(ctx, 2, 0, &v, false, opts->fp64 != 0, opts->update_2d != 0);
     if (rc) return rc;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
@@ -556,12 +569,12 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     }
     if (!ctx->rag_work && (e = hipMalloc(&ctx->rag_work, sizeof(int32_t))) != hipSuccess)
         return hip_fail(e, "hipMalloc");
-    const int slot = v->fp64 ? 2 : (v->waves_per_eu == 4 ? 1 : 0);
-    if (ctx->rag_blocks_per_cu[slot] == 0) {
+    int& bpc = ctx->rag_blocks_per_cu[v->fn];
+    if (bpc == 0) {
         int nb = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, p2r::RAG_W, 0);
         if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-        ctx->rag_blocks_per_cu[slot] = nb > 0 ? nb : 1;
+        bpc = nb > 0 ? nb : 1;
     }
     p2r::RaggedLaunch a{};
     a.n = n_tracks;
@@ -589,7 +602,7 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     a.packed_cap = ctx->rag_packed_cap;
     a.nkeys = nkeys;
     a.nb = (n_tracks + p2r::RAG_W - 1) / p2r::RAG_W;
-    a.grid = std::min(a.nb, ctx->cu_count * ctx->rag_blocks_per_cu[slot]);
+    a.grid = std::min(a.nb, ctx->cu_count * bpc);
     p2r::Params P = params_of(opts);
     hipStream_t s = (hipStream_t)stream;
     if (!opts->use_graph || s == nullptr) {
@@ -849,7 +862,7 @@ int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, vo
     int best_i = -1;
     int cur_w = -1;
     for (size_t i = 0; i < vs.size(); ++i) {
-        if (vs[i].which != which || vs[i].learned || vs[i].fp64) continue;
+        if (vs[i].which != which || vs[i].learned || vs[i].fp64 || vs[i].upd2d) continue;
         if (vs[i].width != cur_w) {
             TRY(p2r::launch_synth(which, vs[i].width, n_tracks, n_layers, surf, trk, hits, s), "synthetic fill");
             cur_w = vs[i].width;

@@ -40,7 +40,7 @@ __device__ __forceinline__ void count_evals(unsigned long long* evals, int iters
 // start of every helix-to-cylinder solve; the whole wave evaluates it on the
 // matrix cores, so every lane stays in the layer loop (lanes past n shadow
 // the last track and write nothing).
-template <int W, int UNROLL, bool LEARNED, typename T = float>
+template <int W, int UNROLL, bool LEARNED, typename T = float, bool U2D = false>
 __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, MlpWeights* Wl) {
     if (LEARNED) {
         const uint32_t* s = reinterpret_cast<const uint32_t*>(a.mlp);
@@ -94,7 +94,7 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
             }
             if (!bad) {
                 T c2 = 0;
-                StepOut o = step_cylinder<T>(st, R, m, V, P, c2, newton_tol(P.tol, R), s_start, T(MLP_ACCEPT_CM));
+                StepOut o = step_cylinder<T, U2D>(st, R, m, V, P, c2, newton_tol(P.tol, R), s_start, T(MLP_ACCEPT_CM));
                 flags |= o.flags;
                 evals += o.iters;
                 if (o.updated) { ++nused; chi2 += c2; }
@@ -195,16 +195,31 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256))) p2z_f64_w
     p2z_body<1, double>(a, P);
 }
 
+// p2r with the update in the hit's (r-phi, z) frame.  Compiled for 4 waves
+// per SIMD (128 VGPRs): the only values that go to scratch memory are the
+// argument copies of the rare FP64 calls.
+#define P2R_2D_KERNEL(W)                                                                  \
+    __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(4)))  \
+    p2r_2d_w##W(FitLaunch a, Params P) { p2r_body<W, 1, false, float, true>(a, P, nullptr); }
+P2R_2D_KERNEL(32)
+P2R_2D_KERNEL(64)
+P2R_2D_KERNEL(128)
+P2R_2D_KERNEL(256)
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256))) p2r_f64_2d_w64(FitLaunch a, Params P) {
+    p2r_body<64, 1, false, double, true>(a, P, nullptr);
+}
+
 P2Z_KERNEL(0, 1)
 P2Z_KERNEL(4, 1)
 P2Z_KERNEL(5, 1)
 P2Z_KERNEL(0, 2)
 
-#define VAR(WH, W, E, U, K) Variant{WH, W, E, U, #K, (const void*)&K, false, false}
-#define VARL(W, E, U, K) Variant{0, W, E, U, #K, (const void*)&K, true, false}
-#define VARD(WH, W, K) Variant{WH, W, 0, 1, #K, (const void*)&K, false, true}
+#define VAR(WH, W, E, U, K) Variant{WH, W, E, U, #K, (const void*)&K, false, false, false}
+#define VARL(W, E, U, K) Variant{0, W, E, U, #K, (const void*)&K, true, false, false}
+#define VARD(WH, W, K) Variant{WH, W, 0, 1, #K, (const void*)&K, false, true, false}
+#define VAR2(W, F64, K) Variant{0, W, 0, 1, #K, (const void*)&K, false, F64, true}
 
-const void* ragged_fit_symbol(int wpe);   // ragged.hip
+const void* ragged_fit_symbol(int wpe, bool fp64, bool u2d);   // ragged.hip
 
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = {
@@ -221,9 +236,16 @@ const std::vector<Variant>& variants() {
         VAR(1, 64, 4, 1, p2z_w64_e4_u1),
         VAR(1, 64, 5, 1, p2z_w64_e5_u1),
         VAR(1, 64, 0, 2, p2z_w64_e0_u2),
-        Variant{2, RAG_W, 0, 1, "rag_fit_e0", ragged_fit_symbol(0), false, false},   // default ragged
-        Variant{2, RAG_W, 4, 1, "rag_fit_e4", ragged_fit_symbol(4), false, false},
-        Variant{2, RAG_W, 0, 1, "rag_fit_f64", ragged_fit_symbol(-1), false, true},
+        Variant{2, RAG_W, 0, 1, "rag_fit_e0", ragged_fit_symbol(0, false, false), false, false, false},   // default ragged
+        Variant{2, RAG_W, 4, 1, "rag_fit_e4", ragged_fit_symbol(4, false, false), false, false, false},
+        Variant{2, RAG_W, 0, 1, "rag_fit_f64", ragged_fit_symbol(0, true, false), false, true, false},
+        Variant{2, RAG_W, 0, 1, "rag_fit_2d", ragged_fit_symbol(0, false, true), false, false, true},
+        Variant{2, RAG_W, 0, 1, "rag_fit_f64_2d", ragged_fit_symbol(0, true, true), false, true, true},
+        VAR2(64, false, p2r_2d_w64),       // update in the hit frame
+        VAR2(32, false, p2r_2d_w32),
+        VAR2(128, false, p2r_2d_w128),
+        VAR2(256, false, p2r_2d_w256),
+        VAR2(64, true, p2r_f64_2d_w64),
         VARD(0, 64, p2r_f64_w64),          // FP64 fits, one per width
         VARD(0, 32, p2r_f64_w32),
         VARD(0, 128, p2r_f64_w128),

@@ -20,6 +20,7 @@ struct Variant {
     const void* fn;   // kernel symbol
     bool learned;     // p2r with the MLP start
     bool fp64;        // every step in FP64 (FP32 inputs and results)
+    bool upd2d;       // cylinders updated in the hit's (r-phi, z) frame
 };
 
 const std::vector<Variant>& variants();

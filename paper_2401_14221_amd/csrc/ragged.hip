@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(256) rag_pack(RaggedLaunch a) {
     }
 }
 
-template <typename T>
+template <typename T, bool U2D>
 __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Params& P, int b, int lane) {
     const int64_t p = (int64_t)b * RAG_W + lane;
     if (p >= a.n) return;
@@ -282,7 +282,7 @@ __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Pa
             T c2 = 0;
             StepOut out;
             if (type == 0.0f) {
-                out = step_cylinder<T>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
+                out = step_cylinder<T, U2D>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
             } else if (type == 1.0f) {
                 out = step_plane<T>(st, v, m, V, P, c2);
             } else {
@@ -302,7 +302,7 @@ __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Pa
 
 // Every wave leaves the loop once the counter passes the last block, so the
 // grid drains whatever its size.
-template <int WPE, typename T>
+template <int WPE, typename T, bool U2D>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 rag_fit(RaggedLaunch a, Params P) {
     const int lane = threadIdx.x;
@@ -311,18 +311,22 @@ rag_fit(RaggedLaunch a, Params P) {
         if (lane == 0) b = atomicAdd(a.work, 1);
         b = __shfl(b, 0);
         if (b >= a.nb) break;
-        fit_sorted_track<T>(a, P, b, lane);
+        fit_sorted_track<T, U2D>(a, P, b, lane);
     }
 }
 
-template __global__ void rag_fit<0, float>(RaggedLaunch, Params);
-template __global__ void rag_fit<4, float>(RaggedLaunch, Params);
-template __global__ void rag_fit<0, double>(RaggedLaunch, Params);
+template __global__ void rag_fit<0, float, false>(RaggedLaunch, Params);
+template __global__ void rag_fit<4, float, false>(RaggedLaunch, Params);
+template __global__ void rag_fit<0, double, false>(RaggedLaunch, Params);
+template __global__ void rag_fit<4, float, true>(RaggedLaunch, Params);
+template __global__ void rag_fit<0, double, true>(RaggedLaunch, Params);
 
-// wpe 0 or 4: the FP32 fit at that occupancy target; -1: the FP64 fit
-const void* ragged_fit_symbol(int wpe) {
-    if (wpe < 0) return (const void*)&rag_fit<0, double>;
-    return wpe == 4 ? (const void*)&rag_fit<4, float> : (const void*)&rag_fit<0, float>;
+// the persistent fit: FP32 at occupancy target wpe (0 or 4), or FP64; the
+// 3D update or the one in the hit frame on cylinders
+const void* ragged_fit_symbol(int wpe, bool fp64, bool u2d) {
+    if (fp64) return u2d ? (const void*)&rag_fit<0, double, true> : (const void*)&rag_fit<0, double, false>;
+    if (u2d) return (const void*)&rag_fit<4, float, true>;   // 128 VGPRs, spills only at the FP64 calls
+    return wpe == 4 ? (const void*)&rag_fit<4, float, false> : (const void*)&rag_fit<0, float, false>;
 }
 
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s) {

@@ -591,7 +591,7 @@ __device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], c
     const bool pd = inv3_spd<T>(S, Si, F32 ? T(PD_TAU32) : T(PD_TAU_F64_FIT));
     uint32_t res = 0;
     bool done = false;                    // the state was updated by the FP64 path
-    if (!F32) {
+    if constexpr (!F32) {
         if (!pd) res = ST_S_NOT_PD;
     } else if (P.fp64_fallback == 2 || !pd) {
         if (!P.fp64_fallback) {
@@ -694,6 +694,173 @@ __device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], c
     return res;
 }
 
+// Update on a cylinder in the hit's (r-phi, z) frame.  With (c, s) the
+// hit's direction in the transverse plane only the two coordinates along the
+// surface are measured: u = -s x + c y (u_hit = 0) and z, i.e.
+//   H = [[-s, c, 0, 0, 0, 0], [0, 0, 1, 0, 0, 0]],  V2 = R V R^T,
+//   R = [[-s, c, 0], [0, 0, 1]];
+// then S = H C' H^T + V2 (2x2), K = C' H^T S^-1 (6x2), p+ = p' + K r,
+// chi2 = r^T S^-1 r, and the Joseph covariance, evaluated as
+// C+ = M + (K V2 - M H^T) K^T with M = A C' = C' - K (C' H^T)^T, as in the
+// 3D update.  Same skip rules, fallback modes and zero-gain trick as there.
+template <typename T>
+__device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3], const T V[6],
+                                                     const Params& P, T& chi2, uint32_t& flags);
+
+struct Fp64Io2 {
+    float p[6], c[21], m[3], V[6], chi2;
+};
+
+// FP64 inverse of the 2x2 S (fallback mode 1), out of line like the full
+// FP64 update: inline, its double divisions would raise the register count
+// of the whole kernel.
+struct Inv2Io {
+    float s00, s01, s11, i00, i01, i11;
+};
+__device__ __noinline__ bool inv2_fp64(Inv2Io* io) {
+    const double d00 = io->s00, d01 = io->s01, d11 = io->s11;
+    const double dd = d00 * d11 - d01 * d01;
+    if (!(d00 > 0.0 && dd > PD_TAU64 * d00 * d11)) return false;
+    io->i00 = (float)(d11 / dd);
+    io->i01 = (float)(-d01 / dd);
+    io->i11 = (float)(d00 / dd);
+    return true;
+}
+__device__ __noinline__ uint32_t kalman_update_2d_fp64(Fp64Io2* io, float chi2_cut);
+
+template <typename T>
+__device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3], const T V[6],
+                                                     const Params& P, T& chi2, uint32_t& flags) {
+    constexpr bool F32 = sizeof(T) == sizeof(float);
+    T* c = st.c;
+    const T rh2 = fma_(m[0], m[0], m[1] * m[1]);
+    const T irh = rcp_(sqrt_start_(rh2));
+    const T ch = m[0] * irh, sh = m[1] * irh;
+    const T v00 = fma_(sh * sh, V[0], fma_(T(-2) * sh * ch, V[1], ch * ch * V[2]));
+    const T v01 = fma_(-sh, V[3], ch * V[4]);
+    const T v11 = V[5];
+    // S = H C' H^T + V2 from the position block alone; P = C' H^T (all six
+    // rows) is formed only after the rare FP64 branch, so that it is not
+    // live across that call
+    const T q0 = fma_(-sh, c[I21(0, 0)], ch * c[I21(0, 1)]);
+    const T q1 = fma_(-sh, c[I21(1, 0)], ch * c[I21(1, 1)]);
+    const T S00 = fma_(-sh, q0, fma_(ch, q1, v00));
+    const T S01 = fma_(-sh, c[I21(2, 0)], ch * c[I21(2, 1)]) + v01;
+    const T S11 = c[I21(2, 2)] + v11;
+    const T det = fma_(S00, S11, -S01 * S01);
+    const T tau = F32 ? T(PD_TAU32) : T(PD_TAU_F64_FIT);
+    const bool pd = S00 > T(0) && det > tau * S00 * S11;
+    T id = rcp_(det);
+    T Si00 = S11 * id, Si01 = -S01 * id, Si11 = S00 * id;
+    uint32_t res = 0;
+    bool done = false;
+    if constexpr (!F32) {
+        if (!pd) res = ST_S_NOT_PD;
+    } else if (P.fp64_fallback == 2 || !pd) {
+        if (!P.fp64_fallback) {
+            res = ST_S_NOT_PD;
+        } else {
+            flags |= ST_FP64_FALLBACK;
+            if (P.fp64_fallback != 1) {
+                Fp64Io2 io;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) io.p[k] = (float)st.p[k];
+#pragma unroll
+                for (int k = 0; k < 21; ++k) io.c[k] = (float)st.c[k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) io.m[k] = (float)m[k];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) io.V[k] = (float)V[k];
+                io.chi2 = (float)chi2;
+                res = kalman_update_2d_fp64(&io, P.chi2_cut);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) st.p[k] = io.p[k];
+#pragma unroll
+                for (int k = 0; k < 21; ++k) st.c[k] = io.c[k];
+                chi2 = io.chi2;
+                done = true;
+            } else {
+                Inv2Io io{(float)S00, (float)S01, (float)S11, 0.0f, 0.0f, 0.0f};
+                if (!inv2_fp64(&io)) res = ST_S_NOT_PD;
+                Si00 = io.i00;
+                Si01 = io.i01;
+                Si11 = io.i11;
+            }
+        }
+    }
+    // P = C' H^T: column 0 = -s C'(:,x) + c C'(:,y), column 1 = C'(:,z)
+    T P0[6], P1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        P0[i] = fma_(-sh, c[I21(i, 0)], ch * c[I21(i, 1)]);
+        P1[i] = c[I21(i, 2)];
+    }
+    // residual in the hit frame from the position differences
+    const T dx = m[0] - st.p[0], dy = m[1] - st.p[1];
+    const T r0 = fma_(-sh, dx, ch * dy);
+    const T r1 = m[2] - st.p[2];
+    T w0 = fma_(Si00, r0, Si01 * r1);
+    T w1 = fma_(Si01, r0, Si11 * r1);
+    const T c2 = fma_(r0, w0, r1 * w1);
+    if (res == 0 && !done && P.chi2_cut > 0.0f && c2 > T(P.chi2_cut)) res = ST_CHI2_CUT;
+    const bool apply = res == 0 && !done;
+    if (apply) chi2 = c2;
+    w0 = apply ? w0 : T(0);
+    w1 = apply ? w1 : T(0);
+    Si00 = apply ? Si00 : T(0);
+    Si01 = apply ? Si01 : T(0);
+    Si11 = apply ? Si11 : T(0);
+    T K0[6], K1[6], KV0[6], KV1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        K0[i] = fma_(P0[i], Si00, P1[i] * Si01);
+        K1[i] = fma_(P0[i], Si01, P1[i] * Si11);
+        KV0[i] = fma_(K0[i], v00, K1[i] * v01);
+        KV1[i] = fma_(K0[i], v01, K1[i] * v11);
+        st.p[i] = fma_(P0[i], w0, fma_(P1[i], w1, st.p[i]));
+    }
+    // M = A C' = C' - K P^T (entries (i, l) with l <= i, and l < 3)
+    T M[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int l = 0; l < 6; ++l)
+            if (l <= i || l < 3) M[i][l] = fma_(-K0[i], P0[l], fma_(-K1[i], P1[l], c[I21(i, l)]));
+    T D0[6], D1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        D0[i] = KV0[i] - fma_(-sh, M[i][0], ch * M[i][1]);
+        D1[i] = KV1[i] - M[i][2];
+    }
+    T n[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int l = 0; l <= i; ++l) n[I21(i, l)] = fma_(D0[i], K0[l], fma_(D1[i], K1[l], M[i][l]));
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c[k] = n[k];
+    return res;
+}
+
+__device__ __noinline__ uint32_t kalman_update_2d_fp64(Fp64Io2* io, float chi2_cut) {
+    StateT<double> sd;
+    for (int k = 0; k < 6; ++k) sd.p[k] = io->p[k];
+    for (int k = 0; k < 21; ++k) sd.c[k] = io->c[k];
+    sd.q = 0.0;
+    double m[3], V[6];
+    for (int k = 0; k < 3; ++k) m[k] = io->m[k];
+    for (int k = 0; k < 6; ++k) V[k] = io->V[k];
+    Params Pd{};
+    Pd.chi2_cut = chi2_cut;
+    double c2 = io->chi2;
+    uint32_t fl = 0;
+    const uint32_t r = kalman_update_2d<double>(sd, m, V, Pd, c2, fl);
+    for (int k = 0; k < 6; ++k) io->p[k] = (float)sd.p[k];
+    for (int k = 0; k < 21; ++k) io->c[k] = (float)sd.c[k];
+    io->chi2 = (float)c2;
+    return r;
+}
+
 // phi into (-pi, pi].  After a layer phi has moved by at most half a turn
 // plus the update's correction, so one conditional 2 pi step is enough; an
 // input far outside the range takes the general reduction first.
@@ -732,7 +899,9 @@ struct StepOut {
     int iters;
 };
 
-template <typename T>
+// U2D: the update in the hit's (r-phi, z) frame (kalman_update_2d), a
+// compile-time choice so that each kernel holds only one update.
+template <typename T, bool U2D = false>
 __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3], const T V[6],
                                                  const Params& P, T& chi2, T tol, T s_start,
                                                  T accept_cm = T(0.0)) {
@@ -788,7 +957,9 @@ __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3
     st.p[2] = fma_(s, cot, st.p[2]);
     st.p[4] = st.p[4] + T(2.0) * h.u;
     transport<0>(J, st.c);
-    uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
+    uint32_t u;
+    if constexpr (U2D) u = kalman_update_2d(st, m, V, P, chi2, o.flags);
+    else u = kalman_update(st, m, V, P, chi2, o.flags);
     o.flags |= u;
     o.updated = (u == 0);
     st.p[4] = wrap_phi(st.p[4]);
