@@ -81,6 +81,7 @@ struct p2r_ctx {
     int32_t* rag_work = nullptr;
     int32_t* rag_perm = nullptr;
     int32_t* rag_keys = nullptr;
+    int64_t* rag_run = nullptr;
     int32_t* rag_blk_off = nullptr;
     float* rag_packed = nullptr;
     int32_t rag_n_cap = 0, rag_nkeys_cap = 0;
@@ -285,8 +286,8 @@ void p2r_ctx_destroy(p2r_ctx* ctx) {
     }
     if (ctx->pipe_start) (void)hipEventDestroy(ctx->pipe_start);
     if (ctx->pipe_surf) (void)hipFree(ctx->pipe_surf);
-    void* bufs[] = {ctx->rag_hist, ctx->rag_base, ctx->rag_work, ctx->rag_perm, ctx->rag_keys, ctx->rag_blk_off,
-                    ctx->rag_packed};
+    void* bufs[] = {ctx->rag_hist, ctx->rag_base, ctx->rag_work, ctx->rag_perm, ctx->rag_keys, ctx->rag_run,
+                    ctx->rag_blk_off, ctx->rag_packed};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete ctx;
@@ -542,10 +543,13 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
             if (*b) (void)hipFree(*b);
             *b = nullptr;
         }
+        if (ctx->rag_run) (void)hipFree(ctx->rag_run);
+        ctx->rag_run = nullptr;
         ctx->rag_n_cap = 0;
         const size_t nb1 = (size_t)(n_tracks + p2r::RAG_W - 1) / p2r::RAG_W + 1;
         if ((e = hipMalloc(&ctx->rag_perm, sizeof(int32_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMalloc(&ctx->rag_keys, sizeof(int32_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&ctx->rag_run, sizeof(int64_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMalloc(&ctx->rag_blk_off, sizeof(int32_t) * nb1)) != hipSuccess) return hip_fail(e, "hipMalloc");
         ctx->rag_n_cap = n_tracks;
     }
@@ -597,6 +601,7 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     a.work = ctx->rag_work;
     a.perm = ctx->rag_perm;
     a.keys = ctx->rag_keys;
+    a.run = ctx->rag_run;
     a.blk_off = ctx->rag_blk_off;
     a.packed = ctx->rag_packed;
     a.packed_cap = ctx->rag_packed_cap;

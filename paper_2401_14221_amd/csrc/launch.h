@@ -69,6 +69,8 @@ struct RaggedLaunch {
     int32_t* work;             // [1] work-queue counter
     int32_t* perm;             // [n] sorted position -> track index
     int32_t* keys;             // [n] sort key of every track
+    int64_t* run;              // [n] sorted position -> the track's first hit | surface count << 56
+                               //     (RAG_RUN_SHIFT), or -1 for a track in the invalid bucket
     int32_t* blk_off;          // [nb + 1] first packed layer row of each block
     float* packed;             // [packed_cap][RAG_FIELDS][RAG_W] hits of the sorted blocks
     int64_t packed_cap;        // layer rows available in packed
@@ -81,6 +83,7 @@ struct RaggedLaunch {
 // need when the CSR ranges do not overlap (blocks that would not fit are
 // reported as BAD_INPUT by the fit).
 int64_t ragged_packed_rows(int64_t n_hits, int lmax);
+constexpr int RAG_RUN_SHIFT = 56;
 int ragged_nkeys(int lmax);
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s);
 

@@ -174,7 +174,14 @@ __global__ void __launch_bounds__(256) rag_scatter(RaggedLaunch a) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int64_t t = t0 + threadIdx.x + j * 256;
-        if (key[j] >= 0) a.perm[off[key[j]] + rank[j]] = (int32_t)t;
+        if (key[j] >= 0) {
+            const int32_t pos = off[key[j]] + rank[j];
+            a.perm[pos] = (int32_t)t;
+            // the track's CSR run in sorted order, so that the pack and the
+            // fit read it sequentially instead of gathering offsets[t]
+            const int L = key_layers(a, key[j]);
+            a.run[pos] = key[j] < a.nkeys - 1 ? (a.offsets[t] | ((int64_t)L << RAG_RUN_SHIFT)) : (int64_t)-1;
+        }
     }
 }
 
@@ -204,9 +211,11 @@ __global__ void __launch_bounds__(256) rag_pack(RaggedLaunch a) {
         int L = 0;
         int64_t h0 = 0;
         if (p < a.n) {
-            const int t = a.perm[p];
-            L = min(key_layers(a, a.keys[t]), rows);   // 0 for an invalid CSR range
-            if (L > 0) h0 = a.offsets[t];
+            const int64_t r = a.run[p];
+            if (r >= 0) {                                // -1: invalid CSR range, no rows
+                L = min((int)(r >> RAG_RUN_SHIFT), rows);
+                h0 = r & (((int64_t)1 << RAG_RUN_SHIFT) - 1);
+            }
         }
         s_rows[tid] = L;
         s_h0[tid] = h0;
@@ -252,15 +261,16 @@ __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Pa
     for (int f = 0; f < 21; ++f) st.c[f] = a.cov_in[(size_t)t * 21 + f];
     const int qi = a.q[t];
     st.q = (T)qi;
-    const int64_t h0 = a.offsets[t];
-    const int64_t L = a.offsets[t + 1] - h0;
+    // run[p]: the surface count of a track whose CSR range the sort found
+    // valid (0 <= L <= lmax, inside [0, n_hits)); -1 for every other track
+    const int64_t r = a.run[p];
+    const int L = r < 0 ? 0 : (int)(r >> RAG_RUN_SHIFT);
     const int64_t o = a.blk_off[b];
     const int rows = a.blk_off[b + 1] - (int32_t)o;
     uint32_t flags = 0;
     int nused = 0;
     T chi2 = 0;
-    if (L < 0 || L > a.lmax || h0 < 0 || h0 + L > a.n_hits || L > rows || (qi != 1 && qi != -1) ||
-        bad_input(st)) {
+    if (r < 0 || L > rows || (qi != 1 && qi != -1) || bad_input(st)) {
         flags = ST_BAD_INPUT;
     } else {
         const float* src = a.packed + (size_t)o * (RAG_FIELDS * RAG_W) + lane;
@@ -280,13 +290,20 @@ __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Pa
                 for (int f = 0; f < RAG_FIELDS; ++f) hb[f] = nx[f * RAG_W];
             }
             T c2 = 0;
-            StepOut out;
-            if (type == 0.0f) {
-                out = step_cylinder<T, U2D>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
-            } else if (type == 1.0f) {
-                out = step_plane<T>(st, v, m, V, P, c2);
+            StepOut out{0u, false, 0};
+            if constexpr (U2D) {
+                // cylinders and planes take different updates
+                if (type == 0.0f) out = step_cylinder<T, true>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
+                else if (type == 1.0f) out = step_plane<T>(st, v, m, V, P, c2);
+                else out.flags = ST_BAD_INPUT;
             } else {
-                out = StepOut{ST_BAD_INPUT, false, 0};
+                // Lanes of one wave may meet cylinders and planes in the same
+                // row: the two propagations diverge, and the update after them
+                // is shared, so such a row costs one update, not two.
+                if (type == 0.0f) out = step_cylinder<T, false, false>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
+                else if (type == 1.0f) out = step_plane<T, false>(st, v, m, V, P, c2);
+                else out.flags = ST_BAD_INPUT;
+                if (out.updated) update_step<T>(st, m, V, P, c2, out);
             }
             flags |= out.flags;
             if (out.updated) { ++nused; chi2 += c2; }

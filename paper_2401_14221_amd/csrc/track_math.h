@@ -892,7 +892,11 @@ __device__ __forceinline__ bool bad_input(const StateT<T>& st) {
 // --------------------------------------------------------- one layer step
 // Cylinder of radius R.  s_start: proposed path length, or NaN for the
 // straight-line start.  Returns the status flags of the layer; on success
-// the state is updated and *updated set.
+// the state is updated and *updated set.  With UPDATE = false a step stops
+// after the propagation (crossing, moved state, transported covariance) and
+// *updated reports that the state was moved; the caller then finishes it
+// with update_step.  A kernel whose lanes meet both kinds of surface in one
+// row so runs one update for both.
 struct StepOut {
     uint32_t flags;
     bool updated;
@@ -901,7 +905,7 @@ struct StepOut {
 
 // U2D: the update in the hit's (r-phi, z) frame (kalman_update_2d), a
 // compile-time choice so that each kernel holds only one update.
-template <typename T, bool U2D = false>
+template <typename T, bool U2D = false, bool UPDATE = true>
 __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3], const T V[6],
                                                  const Params& P, T& chi2, T tol, T s_start,
                                                  T accept_cm = T(0.0)) {
@@ -957,6 +961,10 @@ __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3
     st.p[2] = fma_(s, cot, st.p[2]);
     st.p[4] = st.p[4] + T(2.0) * h.u;
     transport<0>(J, st.c);
+    if constexpr (!UPDATE) {
+        o.updated = true;
+        return o;
+    }
     uint32_t u;
     if constexpr (U2D) u = kalman_update_2d(st, m, V, P, chi2, o.flags);
     else u = kalman_update(st, m, V, P, chi2, o.flags);
@@ -967,7 +975,7 @@ __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3
 }
 
 // Plane z = Z.
-template <typename T>
+template <typename T, bool UPDATE = true>
 __device__ __forceinline__ StepOut step_plane(StateT<T>& st, T Z, const T m[3], const T V[6],
                                               const Params& P, T& chi2) {
     StepOut o{0u, false, 0};
@@ -990,11 +998,25 @@ __device__ __forceinline__ StepOut step_plane(StateT<T>& st, T Z, const T m[3], 
     st.p[2] = Z;
     st.p[4] = st.p[4] + T(2.0) * h.u;
     transport<1>(J, st.c);
+    if constexpr (!UPDATE) {
+        o.updated = true;
+        return o;
+    }
     uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
     o.flags |= u;
     o.updated = (u == 0);
     st.p[4] = wrap_phi(st.p[4]);
     return o;
+}
+
+// The update that ends a step taken with UPDATE = false (3D hit).
+template <typename T>
+__device__ __forceinline__ void update_step(StateT<T>& st, const T m[3], const T V[6], const Params& P,
+                                            T& chi2, StepOut& o) {
+    const uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
+    o.flags |= u;
+    o.updated = (u == 0);
+    st.p[4] = wrap_phi(st.p[4]);
 }
 
 // Newton tolerance for a cylinder of radius R: max(tol, 2 ulp(R)).
