@@ -188,22 +188,28 @@ __global__ void __launch_bounds__(256) rag_scatter(RaggedLaunch a) {
 // One workgroup of 256 threads per block of RAG_W sorted tracks.  Row j of
 // the block holds, for field f and the track at sorted position 64 b + l,
 // packed[((blk_off[b] + j) RAG_FIELDS + f) RAG_W + l].  The rows are built in
-// LDS tiles of up to PACK_ROWS rows for PACK_TRACKS tracks: for each track,
-// one wave reads the track's contiguous run from each CSR array with
-// consecutive lanes on consecutive elements (whole runs, so every fetched
-// cache line is used), and scatters the values into the tile's columns; the
-// tile then goes out as 64-byte pieces of the block's rows, which the L2
-// merges into whole lines.  Tile entries of a track with fewer rows keep
-// stale values, which the fit never reads (it stops at the track's count).
+// LDS tiles of up to PACK_ROWS rows for PACK_TRACKS tracks.  Filling a tile,
+// the workgroup's threads cover each CSR array's runs of the tile's tracks
+// with consecutive threads on consecutive elements (whole runs, so every
+// fetched cache line is used), and each thread issues all of its loads
+// (about 17) before it stores any of them, so that enough reads are in
+// flight to cover the memory latency.  The tile is track-major with an odd
+// track stride: the fill's stores and the drain's loads are free of bank
+// conflicts.  It then goes out as 64-byte pieces of the block's rows, which
+// the L2 merges into whole lines.  Tile entries of a track with fewer rows
+// keep stale values, which the fit never reads (it stops at the track's
+// count).
 constexpr int PACK_ROWS = 24;
 constexpr int PACK_TRACKS = 16;
+constexpr int PACK_TSTRIDE = PACK_ROWS * RAG_FIELDS + 1;
+constexpr int PACK_THREADS = 256;
 
-__global__ void __launch_bounds__(256) rag_pack(RaggedLaunch a) {
-    __shared__ float tile[PACK_ROWS * RAG_FIELDS * PACK_TRACKS];
+__global__ void __launch_bounds__(PACK_THREADS) rag_pack(RaggedLaunch a) {
+    __shared__ float tile[PACK_TRACKS * PACK_TSTRIDE];
     __shared__ int32_t s_rows[RAG_W];
     __shared__ int64_t s_h0[RAG_W];
     const int b = blockIdx.x;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int64_t o = a.blk_off[b];
     const int rows = a.blk_off[b + 1] - (int32_t)o;
     if (tid < RAG_W) {
@@ -221,29 +227,82 @@ __global__ void __launch_bounds__(256) rag_pack(RaggedLaunch a) {
         s_h0[tid] = h0;
     }
     __syncthreads();
+    // per-track element counts of a full tile, and each thread's slots
+    constexpr int NCOV = 6 * PACK_ROWS, NPOS = 3 * PACK_ROWS, NSUR = PACK_ROWS;
+    constexpr int SC = (PACK_TRACKS * NCOV + PACK_THREADS - 1) / PACK_THREADS;
+    constexpr int SP = (PACK_TRACKS * NPOS + PACK_THREADS - 1) / PACK_THREADS;
+    constexpr int SS = (PACK_TRACKS * NSUR + PACK_THREADS - 1) / PACK_THREADS;
     float* dst = a.packed + (size_t)o * (RAG_FIELDS * RAG_W);
+    __shared__ int32_t t_rows[PACK_TRACKS];              // rows of each tile track (<= 0: none)
+    __shared__ int64_t t_h[PACK_TRACKS];                 // and its first hit in the tile
     for (int c0 = 0; c0 < rows; c0 += PACK_ROWS) {
         const int nr = min(PACK_ROWS, rows - c0);
+        // The block's first track has the most rows (counts fall along the
+        // sorted order), rows of them, so its hit c0 exists: slots that have
+        // no element of their own load that one, which keeps every load
+        // unconditional, and do not store it.
+        const int64_t hsafe = s_h0[0] + c0;
         for (int k0 = 0; k0 < RAG_W; k0 += PACK_TRACKS) {
+            if (tid < PACK_TRACKS) {
+                t_rows[tid] = min(nr, s_rows[k0 + tid] - c0);
+                t_h[tid] = s_h0[k0 + tid] + c0;
+            }
+            __syncthreads();
+            // element index of every slot in its array (the safe one when idle)
+            int64_t ic[SC], ip[SP], is[SS];
+            bool okc[SC], okp[SP], oks[SS];
 #pragma unroll
-            for (int i = 0; i < PACK_TRACKS / 4; ++i) {
-                const int kt = wave + 4 * i;                   // track within the tile
-                const int m = min(nr, s_rows[k0 + kt] - c0);   // its rows in this tile
-                if (m <= 0) continue;
-                const int64_t h = s_h0[k0 + kt] + c0;
-                for (int e = lane; e < 6 * m; e += 64)
-                    tile[((e / 6) * RAG_FIELDS + 5 + e % 6) * PACK_TRACKS + kt] = a.hcov[h * 6 + e];
-                for (int e = lane; e < 3 * m; e += 64)
-                    tile[((e / 3) * RAG_FIELDS + 2 + e % 3) * PACK_TRACKS + kt] = a.hpos[h * 3 + e];
-                if (lane < m) {
-                    tile[(lane * RAG_FIELDS + 1) * PACK_TRACKS + kt] = a.sval[h + lane];
-                    tile[(lane * RAG_FIELDS) * PACK_TRACKS + kt] = (float)a.stype[h + lane];
+            for (int i = 0; i < SC; ++i) {
+                const int slot = tid + PACK_THREADS * i, kt = min(slot / NCOV, PACK_TRACKS - 1), e = slot - kt * NCOV;
+                okc[i] = slot < PACK_TRACKS * NCOV && e < 6 * t_rows[kt];
+                ic[i] = okc[i] ? t_h[kt] * 6 + e : hsafe * 6;
+            }
+#pragma unroll
+            for (int i = 0; i < SP; ++i) {
+                const int slot = tid + PACK_THREADS * i, kt = min(slot / NPOS, PACK_TRACKS - 1), e = slot - kt * NPOS;
+                okp[i] = slot < PACK_TRACKS * NPOS && e < 3 * t_rows[kt];
+                ip[i] = okp[i] ? t_h[kt] * 3 + e : hsafe * 3;
+            }
+#pragma unroll
+            for (int i = 0; i < SS; ++i) {
+                const int slot = tid + PACK_THREADS * i, kt = min(slot / NSUR, PACK_TRACKS - 1), e = slot - kt * NSUR;
+                oks[i] = slot < PACK_TRACKS * NSUR && e < t_rows[kt];
+                is[i] = oks[i] ? t_h[kt] + e : hsafe;
+            }
+            float vc[SC], vp[SP], vs[SS], vt[SS];
+#pragma unroll
+            for (int i = 0; i < SC; ++i) vc[i] = a.hcov[ic[i]];
+#pragma unroll
+            for (int i = 0; i < SP; ++i) vp[i] = a.hpos[ip[i]];
+#pragma unroll
+            for (int i = 0; i < SS; ++i) {
+                vs[i] = a.sval[is[i]];
+                vt[i] = (float)a.stype[is[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < SC; ++i) {
+                const int slot = tid + PACK_THREADS * i, kt = slot / NCOV, e = slot - kt * NCOV;
+                if (okc[i]) tile[kt * PACK_TSTRIDE + (e / 6) * RAG_FIELDS + 5 + e % 6] = vc[i];
+            }
+#pragma unroll
+            for (int i = 0; i < SP; ++i) {
+                const int slot = tid + PACK_THREADS * i, kt = slot / NPOS, e = slot - kt * NPOS;
+                if (okp[i]) tile[kt * PACK_TSTRIDE + (e / 3) * RAG_FIELDS + 2 + e % 3] = vp[i];
+            }
+#pragma unroll
+            for (int i = 0; i < SS; ++i) {
+                const int slot = tid + PACK_THREADS * i, kt = slot / NSUR, e = slot - kt * NSUR;
+                if (oks[i]) {
+                    tile[kt * PACK_TSTRIDE + e * RAG_FIELDS + 1] = vs[i];
+                    tile[kt * PACK_TSTRIDE + e * RAG_FIELDS] = vt[i];
                 }
             }
             __syncthreads();
             float* d = dst + (size_t)c0 * (RAG_FIELDS * RAG_W) + k0;
-            for (int e = tid; e < nr * RAG_FIELDS * PACK_TRACKS; e += 256)
-                d[(size_t)(e / PACK_TRACKS) * RAG_W + e % PACK_TRACKS] = tile[e];
+            for (int e = tid; e < nr * RAG_FIELDS * PACK_TRACKS; e += PACK_THREADS) {
+                const int rf = e / PACK_TRACKS, kt = e % PACK_TRACKS;   // rf = row * RAG_FIELDS + field
+                d[(size_t)rf * RAG_W + kt] = tile[kt * PACK_TSTRIDE + rf];
+            }
             __syncthreads();
         }
     }
@@ -357,7 +416,7 @@ hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& 
         hipLaunchKernelGGL(rag_hist, dim3((unsigned)nwg), dim3(tb), lds_keys, s, aa);
         hipLaunchKernelGGL(rag_scan, dim3(1), dim3(1024), lds_keys, s, aa);
         hipLaunchKernelGGL(rag_scatter, dim3((unsigned)nwg), dim3(tb), 2 * lds_keys, s, aa);
-        hipLaunchKernelGGL(rag_pack, dim3(a.nb), dim3(256), 0, s, aa);
+        hipLaunchKernelGGL(rag_pack, dim3(a.nb), dim3(PACK_THREADS), 0, s, aa);
         void* args[] = {&aa, &pp};
         hipError_t e = hipLaunchKernel(v.fn, dim3(a.grid), dim3(RAG_W), args, 0, s);
         if (e != hipSuccess) return e;
