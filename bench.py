@@ -90,20 +90,40 @@ def log(*a):
 
 
 def timed(fn, steps, warmup, stream):
+    """Mean device time of one step over `steps` steps (HIP events on `stream`
+    around them, after `warmup` untimed steps and a synchronisation), the
+    host wall time per step, and the standard deviation of the per-step
+    times (events recorded between the steps)."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
+    ev[0].record(stream)
+    for i in range(steps):
         fn()
-    e1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return ev[0].elapsed_time(ev[steps]) / steps, wall / steps * 1e3, float(per.std())
+
+
+def copy_bandwidth(dev, stream):
+    """GB/s of a plain 1 GiB device-to-device copy (bytes read + written): the
+    bandwidth a streaming kernel can reach, next to the published peak."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+
+    def cp():
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+
+    ms, _, _ = timed(cp, 5, 2, stream)
+    del src, dst
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
 def main():
@@ -174,7 +194,8 @@ def main():
         print(json.dumps({"sweep": rec, "kernel_source_hash": kernel_source_hash()}))
         return
 
-    ms, wall_ms = timed(step, args.steps, args.warmup, stream)
+    ms, wall_ms, ms_std = timed(step, args.steps, args.warmup, stream)
+    copy_gbps = copy_bandwidth(dev, stream)
     tl = n * L
     value = tl / (ms * 1e-3)
     st = out[2].cpu().numpy().view(np.uint32)
@@ -194,12 +215,12 @@ def main():
                      "frac": tflops / FP32_PEAK_TFLOPS, "traffic": measured_traffic(ctx.variant_name(0)),
                      "kernel": ctx.variant_name(0), "flop_per_track_layer": P2R_FLOP_PER_TL},
         "hbm": {"achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
-                "bytes_per_launch": alg_bytes},
+                "bytes_per_launch": alg_bytes, "copy_measured": copy_gbps, "frac_of_copy": gbps / copy_gbps},
         "fit": {"updates_applied": int(nused.sum()), "track_layers": tl,
                 "fp64_fallbacks": int(((st & p2r.ST_FP64_FALLBACK) != 0).sum()),
                 "no_crossing_tracks": int(((st & p2r.ST_NO_CROSSING) != 0).sum()),
                 "newton_fail_tracks": int(((st & p2r.ST_NEWTON_FAIL) != 0).sum()),
-                "wall_ms_per_step": wall_ms},
+                "wall_ms_per_step": wall_ms, "ms_per_step_std": ms_std},
     }
     res["config"]["kernel_source_hash"] = kernel_source_hash()
     if not args.no_extra:
@@ -210,7 +231,7 @@ def main():
         def step_cf():
             ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts_cf, stream=stream)
 
-        ms_cf, _ = timed(step_cf, args.steps, args.warmup, stream)
+        ms_cf, _, _ = timed(step_cf, args.steps, args.warmup, stream)
         res["closed_form_start"] = {"ms_per_step": ms_cf, "value": tl / (ms_cf * 1e-3), "unit": UNIT}
         log(f"p2r closed-form start: {ms_cf:.3f} ms/step")
         # the update in the hit's (r-phi, z) frame (two measured coordinates)
@@ -219,7 +240,7 @@ def main():
         def step_2d():
             ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts_2d, stream=stream)
 
-        ms_2d, _ = timed(step_2d, args.steps, args.warmup, stream)
+        ms_2d, _, _ = timed(step_2d, args.steps, args.warmup, stream)
         res["update_2d"] = {"ms_per_step": ms_2d, "value": tl / (ms_2d * 1e-3), "unit": UNIT,
                             "note": "Kalman update in the hit's (r-phi, z) frame, chi2 with 2 dof"}
         log(f"p2r hit-frame update: {ms_2d:.3f} ms/step")
@@ -229,7 +250,7 @@ def main():
         def step_64():
             ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts_64, stream=stream)
 
-        ms_64, _ = timed(step_64, max(3, args.steps // 2), 1, stream)
+        ms_64, _, _ = timed(step_64, max(3, args.steps // 2), 1, stream)
         res["fp64"] = {"ms_per_step": ms_64, "value": tl / (ms_64 * 1e-3), "unit": UNIT,
                        "note": "every step in FP64 on the same FP32 inputs; results rounded to FP32"}
         log(f"p2r FP64: {ms_64:.3f} ms/step")
@@ -268,13 +289,13 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
     def step():
         ctx.p2z_propagate_update(n, zs, trk, hits, out=o, opts=opts, stream=stream)
 
-    ms, _ = timed(step, args.steps, args.warmup, stream)
+    ms, _, _ = timed(step, args.steps, args.warmup, stream)
     opts_64 = p2r._lib.default_opts(fp64=1)
 
     def step_64():
         ctx.p2z_propagate_update(n, zs, trk, hits, out=o, opts=opts_64, stream=stream)
 
-    ms_64, _ = timed(step_64, max(3, args.steps // 2), 1, stream)
+    ms_64, _, _ = timed(step_64, max(3, args.steps // 2), 1, stream)
     out_h = torch.empty_like(trk_h).pin_memory()
     c2_h = torch.empty(n, dtype=torch.float32).pin_memory()
     st_h = torch.empty(n, dtype=torch.int32).pin_memory()
@@ -288,13 +309,13 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
             c2_h.copy_(o[1], non_blocking=True)
             st_h.copy_(o[2], non_blocking=True)
 
-    ms_x, _ = timed(step_xfer, max(3, args.steps // 2), 1, stream)
+    ms_x, _, _ = timed(step_xfer, max(3, args.steps // 2), 1, stream)
     zs_h = torch.as_tensor(d["surf"], dtype=torch.float32)
 
     def step_pipe():
         ctx.propagate_update_host(1, n, zs_h, trk_h, hits_h, out=(out_h, c2_h, st_h), opts=opts, stream=stream)
 
-    ms_p, _ = timed(step_pipe, max(3, args.steps // 2), 1, stream)
+    ms_p, _, _ = timed(step_pipe, max(3, args.steps // 2), 1, stream)
     tl = n * L
     alg = n * TRACK_BYTES + tl * HIT_BYTES
     out = {"workload": cfg.name, "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT,
@@ -335,11 +356,11 @@ def ragged_leg(ctx, args, stream, ev, p2r, dev):
         ctx.fit_tracks_batched(off, stype, sval, hpos, hcov, par, cov, q, H, lmax, out=ro, opts=ropts,
                                stream=stream)
 
-    ms_r, _ = timed(rstep, args.steps, args.warmup, stream)
+    ms_r, _, _ = timed(rstep, args.steps, args.warmup, stream)
     alg_r = n * (TRACK_BYTES + 8) + H * (HIT_BYTES + 5)
     out = {"workload": cfg.name, "ms_per_step": ms_r, "value": H / (ms_r * 1e-3), "unit": UNIT,
            "track_layers": H, "hbm_frac": alg_r / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-           "variant": ctx.variant_name(2), "note": "one HIP graph per step: sort + persistent fit"}
+           "variant": ctx.variant_name(2), "note": "one HIP graph per step: sort, pack, fit"}
     log(f"ragged: {ms_r:.3f} ms/step, {H / (ms_r * 1e-3):.3e} track-layers/s")
     return out
 
@@ -374,7 +395,7 @@ def learned_leg(ctx, args, stream, ev, p2r, dev):
         def step():
             ctx.p2r_propagate_update(n, radii, trk, hits, out=o, opts=opts, stream=stream)
 
-        ms, _ = timed(step, args.steps, args.warmup, stream)
+        ms, _, _ = timed(step, args.steps, args.warmup, stream)
         cnt = torch.zeros(1, dtype=torch.int64, device=dev)
         opts.helix_evals = cnt.data_ptr()
         step()

@@ -173,8 +173,10 @@ int p2z_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_trac
  *   skips that surface and sets BAD_INPUT.
  * The tracks are counting-sorted on the device by (surface count, |eta|
  * bin); the hits of every block of 64 sorted tracks are packed into
- * coalesced rows, and one persistent kernel whose waves take blocks from an
- * atomic counter fits them.  The six kernels run as one HIP graph, captured
+ * coalesced rows, and a fit kernel with one wave per block fits them, the
+ * longest blocks first (the variants rag_fit_e0 / rag_fit_e4, selected with
+ * p2r_set_variant, fit them with a persistent grid whose waves take blocks
+ * from an atomic counter instead).  The six kernels run as one HIP graph, captured
  * on the first call for a given set of arguments and replayed afterwards
  * (opts->use_graph, non-NULL stream).  The workspace (sort arrays, 16 B per
  * track; packed hits, 44 B per surface plus a few rows per sort key) lives

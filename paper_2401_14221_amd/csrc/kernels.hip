@@ -219,7 +219,8 @@ P2Z_KERNEL(0, 2)
 #define VARD(WH, W, K) Variant{WH, W, 0, 1, #K, (const void*)&K, false, true, false}
 #define VAR2(W, F64, K) Variant{0, W, 0, 1, #K, (const void*)&K, false, F64, true}
 
-const void* ragged_fit_symbol(int wpe, bool fp64, bool u2d);   // ragged.hip
+const void* ragged_grid_symbol(bool fp64, bool u2d);   // ragged.hip
+const void* ragged_fit_symbol(int wpe);
 
 const std::vector<Variant>& variants() {
     static const std::vector<Variant> v = {
@@ -236,11 +237,13 @@ const std::vector<Variant>& variants() {
         VAR(1, 64, 4, 1, p2z_w64_e4_u1),
         VAR(1, 64, 5, 1, p2z_w64_e5_u1),
         VAR(1, 64, 0, 2, p2z_w64_e0_u2),
-        Variant{2, RAG_W, 0, 1, "rag_fit_e0", ragged_fit_symbol(0, false, false), false, false, false},   // default ragged
-        Variant{2, RAG_W, 4, 1, "rag_fit_e4", ragged_fit_symbol(4, false, false), false, false, false},
-        Variant{2, RAG_W, 0, 1, "rag_fit_f64", ragged_fit_symbol(0, true, false), false, true, false},
-        Variant{2, RAG_W, 0, 1, "rag_fit_2d", ragged_fit_symbol(0, false, true), false, false, true},
-        Variant{2, RAG_W, 0, 1, "rag_fit_f64_2d", ragged_fit_symbol(0, true, true), false, true, true},
+        // ragged: one workgroup per block (default), then the persistent work queue
+        Variant{2, RAG_W, 0, 1, "rag_fit_grid", ragged_grid_symbol(false, false), false, false, false, true},
+        Variant{2, RAG_W, 0, 1, "rag_fit_e0", ragged_fit_symbol(0), false, false, false},
+        Variant{2, RAG_W, 4, 1, "rag_fit_e4", ragged_fit_symbol(4), false, false, false},
+        Variant{2, RAG_W, 0, 1, "rag_fit_f64", ragged_grid_symbol(true, false), false, true, false, true},
+        Variant{2, RAG_W, 4, 1, "rag_fit_2d", ragged_grid_symbol(false, true), false, false, true, true},
+        Variant{2, RAG_W, 0, 1, "rag_fit_f64_2d", ragged_grid_symbol(true, true), false, true, true, true},
         VAR2(64, false, p2r_2d_w64),       // update in the hit frame
         VAR2(32, false, p2r_2d_w32),
         VAR2(128, false, p2r_2d_w128),

@@ -21,6 +21,7 @@ struct Variant {
     bool learned;     // p2r with the MLP start
     bool fp64;        // every step in FP64 (FP32 inputs and results)
     bool upd2d;       // cylinders updated in the hit's (r-phi, z) frame
+    bool per_block = false;   // ragged: one workgroup per block instead of the persistent work queue
 };
 
 const std::vector<Variant>& variants();
@@ -41,7 +42,7 @@ hipError_t launch_fit(const Variant& v, const FitLaunch& a, const Params& P, hip
 
 // Ragged path: tracks counting-sorted by (surface count descending, |eta|
 // bin), their hits packed per block of RAG_W sorted tracks into
-// [layer][RAG_FIELDS][RAG_W] rows, then one persistent kernel over the blocks.
+// [layer][RAG_FIELDS][RAG_W] rows, then the fit kernel over the blocks.
 constexpr int RAG_W = 64;
 constexpr int RAG_ETA_BINS = 8;
 constexpr int RAG_FIELDS = 11;      // surface type, surface value, hit (3), hit covariance (6)
@@ -76,7 +77,7 @@ struct RaggedLaunch {
     int64_t packed_cap;        // layer rows available in packed
     int32_t nkeys;
     int32_t nb;                // blocks of RAG_W sorted tracks
-    int32_t grid;              // persistent grid (one wave per workgroup)
+    int32_t grid;              // workgroups of the persistent variant (one wave each)
 };
 
 // Layer rows the packed hits of n tracks with n_hits surfaces in total can

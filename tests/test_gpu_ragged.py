@@ -1,4 +1,5 @@
-"""GPU parity of the ragged batched fit (CSR surfaces, persistent kernel, HIP graph)."""
+"""GPU parity of the ragged batched fit (CSR surfaces, sort, pack, per-block and
+persistent fit kernels, HIP graph)."""
 import numpy as np
 import pytest
 import torch
@@ -56,6 +57,25 @@ def test_ragged_parity_small(ctx):
         print("ragged", use_graph, rep, flush=True)
     L = np.diff(d["offsets"])
     assert np.all(((g["status"] >> 8) & 0xFF) <= L)
+
+
+@pytest.mark.parametrize("variant", ["rag_fit_grid", "rag_fit_e0", "rag_fit_e4"])
+def test_ragged_fit_variants(variant):
+    """Every plain fit kernel (one workgroup per block, and the persistent
+    work queue at both occupancy targets) against the oracle, in a context of
+    its own so that the choice does not leak into the other tests."""
+    assert variant in p2r.variant_names(2)
+    c = p2r.Context(0)
+    try:
+        c.set_variant(2, variant)
+        assert c.variant_name(2) == variant
+        d = ev.make_ragged_event(ev.RAGGED.with_(seed=95), n_tracks=9000)
+        r = oracle.fit_ragged(d, chi2_cut=CUT)
+        fs = final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"])
+        g = run(c, upload(d), int(d["offsets"][-1]), stream=torch.cuda.Stream(), use_graph=1)
+        print(variant, compare(g, r, ctx=variant, final_surface=fs), flush=True)
+    finally:
+        c.close()
 
 
 def test_ragged_graph_replays_match_eager(ctx):
