@@ -57,14 +57,15 @@ def parse():
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources; profiles carry it so stale counter data is not reported."""
+    """Hash of the sources the p2r/p2z kernels are compiled from (kernels.hip
+    and the headers it includes); profiles carry it so that counter data taken
+    from other kernels is not reported."""
     import hashlib
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2401_14221_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in ("kernels.hip", "launch.h", "mlp.h", "mlp_dev.h", "track_math.h"):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
