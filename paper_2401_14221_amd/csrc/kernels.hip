@@ -183,15 +183,18 @@ P2R_LEARNED_KERNEL(128, 0, 1)
 P2R_LEARNED_KERNEL(256, 0, 1)
 P2R_LEARNED_KERNEL(32, 0, 1)
 // FP64 fits: every step in FP64 on the same FP32 inputs, results rounded to
-// FP32 (a precision and throughput reference for the FP32 kernels)
-#define P2R_F64_KERNEL(W)                                                                 \
-    __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256)))               \
+// FP32 (a precision and throughput reference for the FP32 kernels).  Built
+// for 2 waves per SIMD: the state in FP64 needs more than 256 registers, and
+// spilling a few of them (tens of bytes per lane) costs less than running
+// one wave per SIMD with nothing to hide its latencies.
+#define P2R_F64_KERNEL(W)                                                                     \
+    __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2))) \
     p2r_f64_w##W(FitLaunch a, Params P) { p2r_body<W, 1, false, double>(a, P, nullptr); }
 P2R_F64_KERNEL(32)
 P2R_F64_KERNEL(64)
 P2R_F64_KERNEL(128)
 P2R_F64_KERNEL(256)
-__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256))) p2z_f64_w64(FitLaunch a, Params P) {
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2))) p2z_f64_w64(FitLaunch a, Params P) {
     p2z_body<1, double>(a, P);
 }
 
@@ -205,7 +208,7 @@ P2R_2D_KERNEL(32)
 P2R_2D_KERNEL(64)
 P2R_2D_KERNEL(128)
 P2R_2D_KERNEL(256)
-__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256))) p2r_f64_2d_w64(FitLaunch a, Params P) {
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2))) p2r_f64_2d_w64(FitLaunch a, Params P) {
     p2r_body<64, 1, false, double, true>(a, P, nullptr);
 }
 

@@ -414,16 +414,16 @@ rag_fit(RaggedLaunch a, Params P) {
 }
 
 template __global__ void rag_fit_grid<0, float, false>(RaggedLaunch, Params);
-template __global__ void rag_fit_grid<0, double, false>(RaggedLaunch, Params);
+template __global__ void rag_fit_grid<2, double, false>(RaggedLaunch, Params);
 template __global__ void rag_fit_grid<4, float, true>(RaggedLaunch, Params);
-template __global__ void rag_fit_grid<0, double, true>(RaggedLaunch, Params);
+template __global__ void rag_fit_grid<2, double, true>(RaggedLaunch, Params);
 template __global__ void rag_fit<0, float, false>(RaggedLaunch, Params);
 template __global__ void rag_fit<4, float, false>(RaggedLaunch, Params);
 
 // FP32 at occupancy target wpe (0 or 4), or FP64; the 3D update or the one
 // in the hit frame on cylinders (128 VGPRs, spilling only at the FP64 calls)
 const void* ragged_grid_symbol(bool fp64, bool u2d) {
-    if (fp64) return u2d ? (const void*)&rag_fit_grid<0, double, true> : (const void*)&rag_fit_grid<0, double, false>;
+    if (fp64) return u2d ? (const void*)&rag_fit_grid<2, double, true> : (const void*)&rag_fit_grid<2, double, false>;
     return u2d ? (const void*)&rag_fit_grid<4, float, true> : (const void*)&rag_fit_grid<0, float, false>;
 }
 
