@@ -37,8 +37,9 @@ HIT_BYTES = 9 * 4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed steps first: the GPU clocks take some tens of launches to settle")
     ap.add_argument("--no-extra", action="store_true", help="headline p2r figure only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
@@ -251,7 +252,7 @@ def main():
         def step_64():
             ctx.p2r_propagate_update(n, radii, trk, hits, out=out, opts=opts_64, stream=stream)
 
-        ms_64, _, _ = timed(step_64, max(3, args.steps // 2), 1, stream)
+        ms_64, _, _ = timed(step_64, max(3, args.steps // 2), args.warmup, stream)
         res["fp64"] = {"ms_per_step": ms_64, "value": tl / (ms_64 * 1e-3), "unit": UNIT,
                        "note": "every step in FP64 on the same FP32 inputs; results rounded to FP32"}
         log(f"p2r FP64: {ms_64:.3f} ms/step")
@@ -296,7 +297,7 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
     def step_64():
         ctx.p2z_propagate_update(n, zs, trk, hits, out=o, opts=opts_64, stream=stream)
 
-    ms_64, _, _ = timed(step_64, max(3, args.steps // 2), 1, stream)
+    ms_64, _, _ = timed(step_64, max(3, args.steps // 2), args.warmup, stream)
     out_h = torch.empty_like(trk_h).pin_memory()
     c2_h = torch.empty(n, dtype=torch.float32).pin_memory()
     st_h = torch.empty(n, dtype=torch.int32).pin_memory()
@@ -310,13 +311,13 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
             c2_h.copy_(o[1], non_blocking=True)
             st_h.copy_(o[2], non_blocking=True)
 
-    ms_x, _, _ = timed(step_xfer, max(3, args.steps // 2), 1, stream)
+    ms_x, _, _ = timed(step_xfer, max(3, args.steps // 2), args.warmup, stream)
     zs_h = torch.as_tensor(d["surf"], dtype=torch.float32)
 
     def step_pipe():
         ctx.propagate_update_host(1, n, zs_h, trk_h, hits_h, out=(out_h, c2_h, st_h), opts=opts, stream=stream)
 
-    ms_p, _, _ = timed(step_pipe, max(3, args.steps // 2), 1, stream)
+    ms_p, _, _ = timed(step_pipe, max(3, args.steps // 2), args.warmup, stream)
     tl = n * L
     alg = n * TRACK_BYTES + tl * HIT_BYTES
     out = {"workload": cfg.name, "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT,
