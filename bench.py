@@ -277,7 +277,10 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
     cfg = ev.P2Z_THROUGHPUT
     L = len(cfg.surfaces)
     n = cfg.n_total
-    log(f"generating {cfg.name}")
+    if not args.no_autotune:
+        with torch.cuda.stream(stream):
+            ctx.autotune(1, n, L, stream=stream)
+    log(f"p2z variant {ctx.variant_name(1)}; generating {cfg.name}")
     d = ev.make_disk_event(cfg)
     trk_h = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64).pin_memory()
     hits_h = p2r.pack_hits_p2z(d["hits"], d["hitcov"]).pin_memory()
@@ -320,7 +323,8 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
     ms_p, _, _ = timed(step_pipe, max(3, args.steps // 2), args.warmup, stream)
     tl = n * L
     alg = n * TRACK_BYTES + tl * HIT_BYTES
-    out = {"workload": cfg.name, "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT,
+    out = {"workload": cfg.name, "variant": ctx.variant_name(1),
+           "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT,
            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
            "tflops": tl * P2Z_FLOP_PER_TL / (ms * 1e-3) / 1e12,
            "with_transfers": {"ms_per_step": ms_x, "value": tl / (ms_x * 1e-3),
