@@ -273,3 +273,23 @@ def test_closed_form_start_matches_oracle(ctx):
         counts[mode] = float(cnt.item()) / (5000 * 20)
     print("helix evaluations per track-layer: line start %.3f, closed-form start %.3f" % (counts[0], counts[1]))
     assert counts[1] < counts[0]
+
+
+def test_every_plain_variant_matches_oracle():
+    """Each compiled plain p2r / p2z kernel, selected by name, on a ragged-tail workload."""
+    d = ev.make_barrel_event(ev.P2R_THROUGHPUT.with_(seed=91), n_tracks=1000)
+    r = oracle.fit_event(d, "barrel")
+    dz = ev.make_disk_event(ev.P2Z_THROUGHPUT.with_(seed=92), n_tracks=1000)
+    rz = oracle.fit_event(dz, "disk")
+    for which, names in ((0, p2r.variant_names(0)), (1, p2r.variant_names(1))):
+        for name in names:
+            print(f"variant {name}", flush=True)
+            c = p2r.Context(0)
+            c.set_variant(which, name)
+            assert c.variant_name(which) == name
+            if which == 0:
+                W = c.layout_width(0)
+                compare(run_p2r(c, d, W), r, ctx=name)
+            else:
+                compare(run_p2z(c, dz), rz, ctx=name, final_surface="plane")
+            c.close()
