@@ -50,6 +50,8 @@ def parse():
                          "without re-tuning (profiled runs use the variant the timed run chose)")
     ap.add_argument("--sweep-variants", action="store_true",
                     help="run every compiled p2r variant twice on the workload (for per-variant counters)")
+    ap.add_argument("--rag-variant", default=None,
+                    help="time this ragged kernel variant (as reported in the ragged record) without autotuning")
     ap.add_argument("--only", choices=["p2z", "ragged", "learned"], default=None,
                     help="run just this secondary leg and print its record (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -357,6 +359,13 @@ def ragged_leg(ctx, args, stream, ev, p2r, dev):
           torch.empty(n, dtype=torch.int32, device=dev))
     ropts = p2r._lib.default_opts(chi2_cut=30.0)      # outliers up to ~100 sigma: per-hit chi2 cut
     lmax = cfg.extra["lmax"]
+    if args.rag_variant:
+        ctx.set_variant(2, args.rag_variant)
+    elif not args.no_autotune:
+        with torch.cuda.stream(stream):
+            ctx.autotune(2, n, lmax, stream=stream)
+    ctx.reserve(n, lmax)                               # sizing, outside the timed steps
+    log(f"ragged variant {ctx.variant_name(2)}")
 
     def rstep():
         ctx.fit_tracks_batched(off, stype, sval, hpos, hcov, par, cov, q, H, lmax, out=ro, opts=ropts,
@@ -366,7 +375,9 @@ def ragged_leg(ctx, args, stream, ev, p2r, dev):
     alg_r = n * (TRACK_BYTES + 8) + H * (HIT_BYTES + 5)
     out = {"workload": cfg.name, "ms_per_step": ms_r, "value": H / (ms_r * 1e-3), "unit": UNIT,
            "track_layers": H, "hbm_frac": alg_r / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-           "variant": ctx.variant_name(2), "note": "one HIP graph per step: sort, pack, fit"}
+           "variant": ctx.variant_name(2),
+           "note": "one HIP graph per step: counting sort of the tracks, then the fit with the hits staged "
+                   "through LDS"}
     log(f"ragged: {ms_r:.3f} ms/step, {H / (ms_r * 1e-3):.3e} track-layers/s")
     return out
 

@@ -25,11 +25,13 @@
  *    never launch anything.
  *  - Per-track numerical problems are never errors: they are reported in the
  *    status word (P2R_ST_* bits below) and the track keeps its last state.
- *  - The library allocates device memory only in p2r_ctx_create,
- *    p2r_autotune (temporaries), p2r_mlp_create, p2r_mlp_grads/train_step
- *    (gradient partials, when the batch grows) and fit_tracks_batched (its
- *    workspace, when the problem grows, and one graph per argument set);
- *    everything is released by the matching destroy.
+ *  - The library allocates device memory only in its sizing calls:
+ *    p2r_ctx_reserve (the ragged workspace), p2r_ctx_reserve_host (the host
+ *    pipeline's staging), p2r_mlp_create and p2r_mlp_reserve (weights,
+ *    optimiser state, gradient partials), and p2r_autotune (temporaries).
+ *    The fit, pipeline and training calls allocate nothing; a call that needs
+ *    more workspace than was reserved returns P2R_ENOSPACE before launching.
+ *    Everything is released by the matching destroy.
  *
  * Status word per track: bits 0..7 flags, bits 8..15 the number of surfaces
  * whose update was applied, bit 31 set when the track was processed.
@@ -49,6 +51,7 @@ extern "C" {
 #define P2R_ELAYOUT (-2)   /* layout width not supported / misaligned buffer */
 #define P2R_EHIP (-3)      /* a HIP runtime call failed (message has the HIP error) */
 #define P2R_ENOTUNED (-4)  /* no tuned variant and tuning was required */
+#define P2R_ENOSPACE (-5)  /* the workspace reserved in the context is too small for this call */
 
 /* status flags */
 #define P2R_ST_NO_CROSSING (1u << 0)   /* surface not reachable: layer skipped */
@@ -68,6 +71,9 @@ extern "C" {
  * position (x, y, z) and the packed 3x3 covariance (xx, yx, yy, zx, zy, zz). */
 #define P2R_TRACK_FIELDS 28
 #define P2R_HIT_FIELDS 9
+/* Largest n_hits of one fit_tracks_batched call (the ragged fit addresses
+ * its CSR arrays with 32-bit byte offsets: 24 * n_hits < 2^32). */
+#define P2R_MAX_HITS 178956970LL
 
 typedef struct p2r_ctx p2r_ctx; /* opaque: device, tuned variants, workspace, graphs */
 
@@ -111,6 +117,19 @@ const char* p2r_version(void);
  * string) names a JSON file the autotuner reads and writes. */
 int p2r_ctx_create(p2r_ctx** out, int device, const char* tune_cache_path);
 void p2r_ctx_destroy(p2r_ctx* ctx);
+
+/* Size the context's workspace for fit_tracks_batched calls of up to
+ * max_tracks tracks with max_surfaces (0..255) surfaces per track: the sort
+ * arrays (16 B per track) and the sort-key histograms (8 B per key, 8 keys
+ * per surface count).  Grow-only; a call that grows the workspace frees the
+ * old one (no ragged fit of this context may be in flight) and drops the
+ * captured graph.  Synchronous. */
+int p2r_ctx_reserve(p2r_ctx* ctx, int32_t max_tracks, int32_t max_surfaces);
+
+/* Number of device allocations the library has made in this process (all
+ * contexts and MLPs): a diagnostic for callers that must not allocate in
+ * their timed or captured work. */
+unsigned long long p2r_device_allocations(void);
 
 /* Width the context uses for `which` (0 p2r, 1 p2z, 2 ragged). */
 int p2r_layout_width(p2r_ctx* ctx, int which, int32_t* W_out);
@@ -164,38 +183,43 @@ int p2z_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_trac
  * each a cylinder (surf_type 0, surf_val = radius) or a plane (surf_type 1,
  * surf_val = signed z), and one 3D hit per surface.
  *   n_tracks tracks, n_hits = offsets[n_tracks] surfaces in total (host
- *   value, used to check sizes), max_surfaces >= every track's count
- *   (<= 255; a track with more, or a negative count, is BAD_INPUT).
+ *   value, used to check sizes; at most P2R_MAX_HITS), max_surfaces >= every
+ *   track's count (<= 255; a track with more, or a negative count, is
+ *   BAD_INPUT).
  *   offsets [n_tracks+1] (int64, offsets[0] = 0), surf_type [n_hits] (uint8),
  *   surf_val [n_hits], hit_pos [n_hits][3], hit_cov [n_hits][6] (packed),
  *   par_in [n][6], cov_in [n][21], q [n] (int8 +-1); outputs par_out [n][6],
  *   cov_out [n][21], chi2_out [n], status [n].  A surf_type other than 0/1
  *   skips that surface and sets BAD_INPUT.
  * The tracks are counting-sorted on the device by (surface count, |eta|
- * bin); the hits of every block of 64 sorted tracks are packed into
- * coalesced rows, and a fit kernel with one wave per block fits them, the
- * longest blocks first (the variants rag_fit_e0 / rag_fit_e4, selected with
- * p2r_set_variant, fit them with a persistent grid whose waves take blocks
- * from an atomic counter instead).  The six kernels run as one HIP graph, captured
- * on the first call for a given set of arguments and replayed afterwards
- * (opts->use_graph, non-NULL stream).  The workspace (sort arrays, 16 B per
- * track; packed hits, 44 B per surface plus a few rows per sort key) lives
- * in the context, allocated on first use and grown when needed: calls on
- * one context must not overlap.  The CSR ranges of valid tracks must not
- * overlap; tracks whose packed rows would not fit because they do are
- * reported BAD_INPUT. */
+ * bin); a fit kernel with one wave per block of 64 sorted tracks then
+ * streams each block's hits from the CSR arrays through LDS, a few surfaces
+ * at a time, the longest blocks first (the autotuner, or p2r_set_variant,
+ * picks how many surfaces a chunk holds, the occupancy target, prefetching,
+ * and the per-block grid or a persistent grid whose waves take blocks from an
+ * atomic counter).  The kernels run as one HIP graph, captured on the first
+ * call for a given set of arguments and replayed afterwards (opts->use_graph,
+ * non-NULL stream).  The workspace is the one p2r_ctx_reserve sized
+ * (P2R_ENOSPACE if it is too small): calls on one context must not overlap.
+ * CSR ranges may overlap. */
 int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits,
                        int32_t max_surfaces, const int64_t* offsets, const uint8_t* surf_type,
                        const float* surf_val, const float* hit_pos, const float* hit_cov,
                        const float* par_in, const float* cov_in, const int8_t* q, float* par_out,
                        float* cov_out, float* chi2_out, uint32_t* status, void* stream);
 
-/* Autotune `which` (0 p2r, 1 p2z) on synthetic tracks of this shape: times
- * every compiled variant (width, waves per SIMD, layer-loop unroll) with HIP
- * events, keeps the fastest in the context (the default variant unless the
- * fastest beats it by 3% or more) and writes the cache file if the context
- * has one.  Allocates and frees temporary device buffers;
- * synchronises the stream. */
+/* Autotune `which` (0 p2r, 1 p2z, 2 ragged) on synthetic tracks of this
+ * shape: times every compiled plain variant with HIP events, keeps the
+ * fastest in the context (the default variant unless the fastest beats it by
+ * 3% or more) and writes the cache file if the context has one; a shape the
+ * cache already holds for this build of the library (its version string names
+ * the hash of the sources) is served from it without timing.  p2r / p2z:
+ * width, waves per SIMD, layer-loop unroll; n_layers layers.  Ragged:
+ * surfaces per staged chunk, waves per SIMD, prefetch, per-block grid or
+ * persistent queue, on n_tracks tracks of 5..n_layers mixed cylinders and
+ * disks (n_layers = max_surfaces <= 255); it also reserves the ragged
+ * workspace for that shape (p2r_ctx_reserve).  Allocates and frees
+ * temporary device buffers; synchronises the stream. */
 int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, void* stream);
 
 /* Description of the variant in use for `which` (host string owned by ctx). */

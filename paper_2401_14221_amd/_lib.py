@@ -11,7 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libp2r.so")
 _HEADER = os.path.join(os.path.dirname(_HERE), "include", "p2r.h")
 
-P2R_OK, P2R_EINVAL, P2R_ELAYOUT, P2R_EHIP, P2R_ENOTUNED = 0, -1, -2, -3, -4
+P2R_OK, P2R_EINVAL, P2R_ELAYOUT, P2R_EHIP, P2R_ENOTUNED, P2R_ENOSPACE = 0, -1, -2, -3, -4, -5
 ST_NO_CROSSING = 1 << 0
 ST_NEWTON_FAIL = 1 << 1
 ST_FP64_FALLBACK = 1 << 2
@@ -71,6 +71,8 @@ def library():
         L.p2r_variant_at.argtypes = [C.c_int, C.c_int]
         L.p2r_variant_at.restype = C.c_char_p
         L.fit_tracks_batched.argtypes = [vp, C.POINTER(Opts), i32, i64, i32] + [vp] * 13
+        L.p2r_ctx_reserve.argtypes = [vp, i32, i32]
+        L.p2r_device_allocations.restype = C.c_ulonglong
         L.p2r_mlp_create.argtypes = [vp, C.POINTER(vp)]
         L.p2r_mlp_destroy.argtypes = [vp]
         L.p2r_mlp_destroy.restype = None
@@ -85,6 +87,11 @@ def library():
         L.p2r_mlp_load.argtypes = [vp, C.c_char_p]
         _lib = L
     return _lib
+
+
+def device_allocations() -> int:
+    """Device allocations the library has made in this process."""
+    return int(library().p2r_device_allocations())
 
 
 def exported_symbols():
@@ -135,6 +142,7 @@ class Context:
         if not torch.cuda.is_available():
             raise RuntimeError("libp2r needs a HIP GPU; none is visible")
         self.device = device
+        self._ragged_cap = (0, -1)          # (tracks, surfaces per track) reserved
         self._h = vp()
         _check(library().p2r_ctx_create(C.byref(self._h), device,
                                         tune_cache.encode() if tune_cache else None))
@@ -164,6 +172,13 @@ class Context:
 
     def autotune(self, which: int, n_tracks: int, n_layers: int, stream=None):
         _check(library().p2r_autotune(self._h, which, n_tracks, n_layers, _stream(stream)))
+        if which == 2:                      # the ragged tuner reserves the workspace for its shape
+            self._ragged_cap = (max(self._ragged_cap[0], n_tracks), max(self._ragged_cap[1], n_layers))
+
+    def reserve(self, max_tracks: int, max_surfaces: int):
+        """Size the ragged workspace (p2r_ctx_reserve); grow-only."""
+        _check(library().p2r_ctx_reserve(self._h, int(max_tracks), int(max_surfaces)))
+        self._ragged_cap = (max(self._ragged_cap[0], int(max_tracks)), max(self._ragged_cap[1], int(max_surfaces)))
 
     # --------------------------------------------------------------- fits
     def _outputs(self, trk_in, n):
@@ -220,6 +235,10 @@ class Context:
                    torch.empty(n, dtype=torch.float32, device=dev),
                    torch.empty(n, dtype=torch.int32, device=dev))
         par_out, cov_out, chi2, status = out
+        if n > self._ragged_cap[0] or max_surfaces > self._ragged_cap[1]:
+            # sizing happens here, before the C call, which itself never allocates
+            if 0 <= max_surfaces <= 255:
+                self.reserve(max(n, self._ragged_cap[0]), max(max_surfaces, self._ragged_cap[1]))
         _check(library().fit_tracks_batched(self._h, C.byref(opts), n, int(n_hits), int(max_surfaces),
                                             _ptr(offsets), _ptr(surf_type),
                                             _ptr(surf_val), _ptr(hit_pos), _ptr(hit_cov), _ptr(par_in),

@@ -1,6 +1,7 @@
 """Build libp2r.so (HIP, gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -20,9 +21,26 @@ FLAGS = [
 SOURCES = ["kernels.hip", "ragged.hip", "mlp.hip", "capi.cpp"]
 
 
+def source_hash() -> str:
+    """Hash of every source the library is compiled from (the C ABI header
+    included).  It is compiled into the library's version string, which keys
+    the autotuner's cache: a rebuilt kernel is timed again, never served a
+    choice made for other code."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "p2r.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-x", "hip", *srcs, "-o", SO + ".tmp"]
+    cmd = [HIPCC, *FLAGS, f"-DP2R_SRC_HASH=\"{source_hash()}\"", "-I", os.path.join(ROOT, "include"),
+           "-x", "hip", *srcs, "-o", SO + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -38,6 +39,17 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Every device allocation of the library goes through here and is counted
+// (p2r_device_allocations), so that a test can show that a call made after
+// the sizing calls allocates nothing.
+std::atomic<unsigned long long> g_allocs{0};
+template <typename T>
+hipError_t dev_alloc(T** p, size_t bytes) {
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+    if (e == hipSuccess) g_allocs.fetch_add(1, std::memory_order_relaxed);
+    return e;
+}
 
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
@@ -82,10 +94,7 @@ struct p2r_ctx {
     int32_t* rag_perm = nullptr;
     int32_t* rag_keys = nullptr;
     int64_t* rag_run = nullptr;
-    int32_t* rag_blk_off = nullptr;
-    float* rag_packed = nullptr;
-    int32_t rag_n_cap = 0, rag_nkeys_cap = 0;
-    int64_t rag_packed_cap = 0;
+    int32_t rag_n_cap = 0, rag_nkeys_cap = 0, rag_lmax_cap = -1;
     std::map<const void*, int> rag_blocks_per_cu;   // resident workgroups per CU of each persistent fit
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -231,7 +240,12 @@ hipError_t launch_synth(int which, int W, int32_t n, int32_t L, float* surf, flo
 
 extern "C" {
 
-const char* p2r_version(void) { return "p2r-mi355x 0.1"; }
+// The version names the hash of the sources the library was built from
+// (set by the build); the autotuner's cache keys carry it.
+#ifndef P2R_SRC_HASH
+#define P2R_SRC_HASH "unhashed"
+#endif
+const char* p2r_version(void) { return "p2r-mi355x 0.2 src " P2R_SRC_HASH; }
 
 const char* p2r_last_error(void) { return g_err.c_str(); }
 
@@ -286,8 +300,7 @@ void p2r_ctx_destroy(p2r_ctx* ctx) {
     }
     if (ctx->pipe_start) (void)hipEventDestroy(ctx->pipe_start);
     if (ctx->pipe_surf) (void)hipFree(ctx->pipe_surf);
-    void* bufs[] = {ctx->rag_hist, ctx->rag_base, ctx->rag_work, ctx->rag_perm, ctx->rag_keys, ctx->rag_run,
-                    ctx->rag_blk_off, ctx->rag_packed};
+    void* bufs[] = {ctx->rag_hist, ctx->rag_base, ctx->rag_work, ctx->rag_perm, ctx->rag_keys, ctx->rag_run};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete ctx;
@@ -428,14 +441,14 @@ static int propagate_host(int which, p2r_ctx* ctx, const p2r_opts* opts, int32_t
         }
         ctx->pipe_bytes = 0;
         for (int k = 0; k < p2r_ctx::NPIPE; ++k)
-            if ((e = hipMalloc(&ctx->pipe_buf[k], bytes)) != hipSuccess) return hip_fail(e, "hipMalloc");
+            if ((e = dev_alloc(&ctx->pipe_buf[k], bytes)) != hipSuccess) return hip_fail(e, "hipMalloc");
         ctx->pipe_bytes = bytes;
     }
     if (n_layers > ctx->pipe_surf_cap) {
         if (ctx->pipe_surf) (void)hipFree(ctx->pipe_surf);
         ctx->pipe_surf = nullptr;
         ctx->pipe_surf_cap = 0;
-        if ((e = hipMalloc(&ctx->pipe_surf, sizeof(float) * n_layers)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = dev_alloc(&ctx->pipe_surf, sizeof(float) * n_layers)) != hipSuccess) return hip_fail(e, "hipMalloc");
         ctx->pipe_surf_cap = n_layers;
     }
     // the surface table, then the pipeline, after the caller's queued work
@@ -504,6 +517,98 @@ int p2z_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_trac
                           chunk_tracks, stream);
 }
 
+// Launch arguments of the ragged fit over the context's reserved workspace.
+static int ragged_launch_args(p2r_ctx* ctx, const p2r::Variant& v, int32_t n_tracks, int64_t n_hits,
+                              int32_t max_surfaces, const int64_t* offsets, const uint8_t* surf_type,
+                              const float* surf_val, const float* hit_pos, const float* hit_cov,
+                              const float* par_in, const float* cov_in, const int8_t* q, float* par_out,
+                              float* cov_out, float* chi2_out, uint32_t* status, p2r::RaggedLaunch& a) {
+    int& bpc = ctx->rag_blocks_per_cu[v.fn];
+    if (bpc == 0) {
+        int nb = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v.fn, p2r::RAG_W, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        bpc = nb > 0 ? nb : 1;
+    }
+    a = p2r::RaggedLaunch{};
+    a.n = n_tracks;
+    a.lmax = max_surfaces;
+    a.n_hits = n_hits;
+    a.offsets = offsets;
+    a.stype = surf_type;
+    a.sval = surf_val;
+    a.hpos = hit_pos;
+    a.hcov = hit_cov;
+    a.par_in = par_in;
+    a.cov_in = cov_in;
+    a.q = q;
+    a.par_out = par_out;
+    a.cov_out = cov_out;
+    a.chi2 = chi2_out;
+    a.status = status;
+    a.hist = ctx->rag_hist;
+    a.base = ctx->rag_base;
+    a.work = ctx->rag_work;
+    a.perm = ctx->rag_perm;
+    a.keys = ctx->rag_keys;
+    a.run = ctx->rag_run;
+    a.nkeys = p2r::ragged_nkeys(max_surfaces);
+    a.nb = (n_tracks + p2r::RAG_W - 1) / p2r::RAG_W;
+    a.grid = std::min(a.nb, ctx->cu_count * bpc);
+    return P2R_OK;
+}
+
+int p2r_ctx_reserve(p2r_ctx* ctx, int32_t max_tracks, int32_t max_surfaces) {
+    if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
+    if (max_tracks < 0) return fail(P2R_EINVAL, "negative max_tracks");
+    if (max_surfaces < 0 || max_surfaces > 255) return fail(P2R_EINVAL, "max_surfaces must be in [0, 255]");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e;
+    const int nkeys = p2r::ragged_nkeys(max_surfaces);
+    const bool grow_n = max_tracks > ctx->rag_n_cap, grow_k = nkeys > ctx->rag_nkeys_cap;
+    if (grow_n || grow_k) {
+        // a captured graph records the old buffers
+        if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        ctx->exec = nullptr;
+        ctx->graph = nullptr;
+        ctx->have_graph = false;
+    }
+    if (grow_n) {
+        for (int32_t** b : {&ctx->rag_perm, &ctx->rag_keys}) {
+            if (*b) (void)hipFree(*b);
+            *b = nullptr;
+        }
+        if (ctx->rag_run) (void)hipFree(ctx->rag_run);
+        ctx->rag_run = nullptr;
+        ctx->rag_n_cap = 0;
+        const size_t n = (size_t)std::max(max_tracks, 1);
+        if ((e = dev_alloc(&ctx->rag_perm, sizeof(int32_t) * n)) != hipSuccess ||
+            (e = dev_alloc(&ctx->rag_keys, sizeof(int32_t) * n)) != hipSuccess ||
+            (e = dev_alloc(&ctx->rag_run, sizeof(int64_t) * n)) != hipSuccess)
+            return hip_fail(e, "hipMalloc (ragged workspace)");
+        ctx->rag_n_cap = max_tracks;
+    }
+    if (grow_k) {
+        for (int32_t** b : {&ctx->rag_hist, &ctx->rag_base}) {
+            if (*b) (void)hipFree(*b);
+            *b = nullptr;
+        }
+        ctx->rag_nkeys_cap = 0;
+        if ((e = dev_alloc(&ctx->rag_hist, sizeof(int32_t) * nkeys)) != hipSuccess ||
+            (e = dev_alloc(&ctx->rag_base, sizeof(int32_t) * nkeys)) != hipSuccess)
+            return hip_fail(e, "hipMalloc (ragged workspace)");
+        ctx->rag_nkeys_cap = nkeys;
+    }
+    ctx->rag_lmax_cap = std::max(ctx->rag_lmax_cap, max_surfaces);
+    if (!ctx->rag_work && (e = dev_alloc(&ctx->rag_work, sizeof(int32_t))) != hipSuccess)
+        return hip_fail(e, "hipMalloc (ragged workspace)");
+    return P2R_OK;
+}
+
+unsigned long long p2r_device_allocations(void) { return g_allocs.load(std::memory_order_relaxed); }
+
 int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits, int32_t max_surfaces,
                        const int64_t* offsets, const uint8_t* surf_type, const float* surf_val,
                        const float* hit_pos, const float* hit_cov, const float* par_in, const float* cov_in,
@@ -533,81 +638,21 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     if (rc) return rc;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-    hipError_t e;
-    // workspace
+    // the fit addresses the CSR arrays with 32-bit byte offsets (hit_cov, 24 B per surface, the largest)
+    if (n_hits > P2R_MAX_HITS)
+        return fail(P2R_EINVAL, "n_hits %lld too large for one call (at most %lld)", (long long)n_hits,
+                    (long long)P2R_MAX_HITS);
+    // the workspace comes from p2r_ctx_reserve: nothing is allocated here
     const int nkeys = p2r::ragged_nkeys(max_surfaces);
-    const int64_t packed_rows = p2r::ragged_packed_rows(n_hits, max_surfaces);
-    if (packed_rows > INT32_MAX) return fail(P2R_EINVAL, "n_hits %lld too large for one call", (long long)n_hits);
-    if (n_tracks > ctx->rag_n_cap) {
-        for (int32_t** b : {&ctx->rag_perm, &ctx->rag_keys, &ctx->rag_blk_off}) {
-            if (*b) (void)hipFree(*b);
-            *b = nullptr;
-        }
-        if (ctx->rag_run) (void)hipFree(ctx->rag_run);
-        ctx->rag_run = nullptr;
-        ctx->rag_n_cap = 0;
-        const size_t nb1 = (size_t)(n_tracks + p2r::RAG_W - 1) / p2r::RAG_W + 1;
-        if ((e = hipMalloc(&ctx->rag_perm, sizeof(int32_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        if ((e = hipMalloc(&ctx->rag_keys, sizeof(int32_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        if ((e = hipMalloc(&ctx->rag_run, sizeof(int64_t) * n_tracks)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        if ((e = hipMalloc(&ctx->rag_blk_off, sizeof(int32_t) * nb1)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        ctx->rag_n_cap = n_tracks;
-    }
-    if (nkeys > ctx->rag_nkeys_cap) {
-        for (int32_t** b : {&ctx->rag_hist, &ctx->rag_base}) {
-            if (*b) (void)hipFree(*b);
-            *b = nullptr;
-        }
-        ctx->rag_nkeys_cap = 0;
-        if ((e = hipMalloc(&ctx->rag_hist, sizeof(int32_t) * nkeys)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        if ((e = hipMalloc(&ctx->rag_base, sizeof(int32_t) * nkeys)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        ctx->rag_nkeys_cap = nkeys;
-    }
-    if (packed_rows > ctx->rag_packed_cap) {
-        if (ctx->rag_packed) (void)hipFree(ctx->rag_packed);
-        ctx->rag_packed = nullptr;
-        ctx->rag_packed_cap = 0;
-        const size_t bytes = sizeof(float) * (size_t)packed_rows * p2r::RAG_FIELDS * p2r::RAG_W;
-        if ((e = hipMalloc(&ctx->rag_packed, bytes)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        ctx->rag_packed_cap = packed_rows;
-    }
-    if (!ctx->rag_work && (e = hipMalloc(&ctx->rag_work, sizeof(int32_t))) != hipSuccess)
-        return hip_fail(e, "hipMalloc");
-    int& bpc = ctx->rag_blocks_per_cu[v->fn];
-    if (bpc == 0) {
-        int nb = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, p2r::RAG_W, 0);
-        if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-        bpc = nb > 0 ? nb : 1;
-    }
+    if (n_tracks > ctx->rag_n_cap || nkeys > ctx->rag_nkeys_cap || !ctx->rag_work)
+        return fail(P2R_ENOSPACE, "ragged workspace reserved for %d tracks and %d surfaces per track; this call "
+                    "needs %d and %d: call p2r_ctx_reserve first", ctx->rag_n_cap, ctx->rag_lmax_cap, n_tracks,
+                    max_surfaces);
+    hipError_t e;
     p2r::RaggedLaunch a{};
-    a.n = n_tracks;
-    a.lmax = max_surfaces;
-    a.n_hits = n_hits;
-    a.offsets = offsets;
-    a.stype = surf_type;
-    a.sval = surf_val;
-    a.hpos = hit_pos;
-    a.hcov = hit_cov;
-    a.par_in = par_in;
-    a.cov_in = cov_in;
-    a.q = q;
-    a.par_out = par_out;
-    a.cov_out = cov_out;
-    a.chi2 = chi2_out;
-    a.status = status;
-    a.hist = ctx->rag_hist;
-    a.base = ctx->rag_base;
-    a.work = ctx->rag_work;
-    a.perm = ctx->rag_perm;
-    a.keys = ctx->rag_keys;
-    a.run = ctx->rag_run;
-    a.blk_off = ctx->rag_blk_off;
-    a.packed = ctx->rag_packed;
-    a.packed_cap = ctx->rag_packed_cap;
-    a.nkeys = nkeys;
-    a.nb = (n_tracks + p2r::RAG_W - 1) / p2r::RAG_W;
-    a.grid = std::min(a.nb, ctx->cu_count * bpc);
+    if ((rc = ragged_launch_args(ctx, *v, n_tracks, n_hits, max_surfaces, offsets, surf_type, surf_val, hit_pos,
+                                 hit_cov, par_in, cov_in, q, par_out, cov_out, chi2_out, status, a)))
+        return rc;
     p2r::Params P = params_of(opts);
     hipStream_t s = (hipStream_t)stream;
     if (!opts->use_graph || s == nullptr) {
@@ -664,7 +709,7 @@ int p2r_mlp_create(p2r_ctx* ctx, p2r_mlp** out) {
     const size_t np = p2r::MLP_NPARAM;
     const size_t fl = (4 * np + 64) * sizeof(float);
     const size_t bytes = fl + sizeof(p2r::MlpWeights) + 256;
-    hipError_t e = hipMalloc(&m->block, bytes);
+    hipError_t e = dev_alloc(&m->block, bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
     if ((e = hipMemset(m->block, 0, bytes)) != hipSuccess) { (void)hipFree(m->block); return hip_fail(e, "hipMemset"); }
     float* f = static_cast<float*>(m->block);
@@ -695,7 +740,7 @@ static int mlp_reserve(p2r_mlp* m, int32_t B) {
     if (m->d.part) (void)hipFree(m->d.part);
     m->d.part = nullptr;
     m->d.part_blocks = 0;
-    hipError_t e = hipMalloc(&m->d.part, (size_t)nb * (p2r::MLP_NPARAM + 1) * sizeof(float));
+    hipError_t e = dev_alloc(&m->d.part, (size_t)nb * (p2r::MLP_NPARAM + 1) * sizeof(float));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
     m->d.part_blocks = nb;
     return P2R_OK;
@@ -818,10 +863,100 @@ int p2r_mlp_load(p2r_mlp* m, const char* path) {
 }
 
 
+// Ragged autotune: every plain ragged variant (chunk of staged surfaces,
+// waves per SIMD, per-block grid or persistent queue, prefetch) timed on
+// synthetic tracks with n surfaces each drawn from 5 .. lmax, mixed
+// cylinders and disks in crossing order.  Reserves the context's ragged
+// workspace for this shape.
+static int autotune_ragged(p2r_ctx* ctx, const std::string& key, int32_t n, int32_t lmax, hipStream_t s) {
+    const auto& vs = p2r::variants();
+    std::vector<int64_t> off((size_t)n + 1, 0);
+    for (int32_t t = 0; t < n; ++t) off[t + 1] = off[t] + p2r::ragged_synth_count(t, lmax);
+    const int64_t H = off[n];
+    if (H > P2R_MAX_HITS) return fail(P2R_EINVAL, "ragged autotune: too many surfaces");
+    int rc = p2r_ctx_reserve(ctx, n, lmax);
+    if (rc) return rc;
+    int64_t* d_off = nullptr;
+    uint8_t* d_st = nullptr;
+    float *d_sv = nullptr, *d_hp = nullptr, *d_hc = nullptr, *d_par = nullptr, *d_cov = nullptr;
+    float *d_po = nullptr, *d_co = nullptr, *d_c2 = nullptr;
+    int8_t* d_q = nullptr;
+    uint32_t* d_status = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&]() {
+        for (void* p : {(void*)d_off, (void*)d_st, (void*)d_sv, (void*)d_hp, (void*)d_hc, (void*)d_par, (void*)d_cov,
+                        (void*)d_po, (void*)d_co, (void*)d_c2, (void*)d_q, (void*)d_status})
+            if (p) (void)hipFree(p);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+#define TRY(x, what)                              \
+    do {                                          \
+        e = (x);                                  \
+        if (e != hipSuccess) {                    \
+            cleanup();                            \
+            return hip_fail(e, what);             \
+        }                                         \
+    } while (0)
+    const size_t h1 = (size_t)std::max<int64_t>(H, 1);
+    TRY(dev_alloc(&d_off, sizeof(int64_t) * (n + 1)), "hipMalloc");
+    TRY(dev_alloc(&d_st, h1), "hipMalloc");
+    TRY(dev_alloc(&d_sv, sizeof(float) * h1), "hipMalloc");
+    TRY(dev_alloc(&d_hp, sizeof(float) * 3 * h1), "hipMalloc");
+    TRY(dev_alloc(&d_hc, sizeof(float) * 6 * h1), "hipMalloc");
+    TRY(dev_alloc(&d_par, sizeof(float) * 6 * n), "hipMalloc");
+    TRY(dev_alloc(&d_cov, sizeof(float) * 21 * n), "hipMalloc");
+    TRY(dev_alloc(&d_po, sizeof(float) * 6 * n), "hipMalloc");
+    TRY(dev_alloc(&d_co, sizeof(float) * 21 * n), "hipMalloc");
+    TRY(dev_alloc(&d_c2, sizeof(float) * n), "hipMalloc");
+    TRY(dev_alloc(&d_q, (size_t)n), "hipMalloc");
+    TRY(dev_alloc(&d_status, sizeof(uint32_t) * n), "hipMalloc");
+    TRY(hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    TRY(p2r::launch_ragged_synth(n, lmax, d_off, d_st, d_sv, d_hp, d_hc, d_par, d_cov, d_q, s), "synthetic fill");
+    TRY(hipEventCreate(&e0), "hipEventCreate");
+    TRY(hipEventCreate(&e1), "hipEventCreate");
+    p2r_opts o;
+    p2r_opts_default(&o);
+    o.chi2_cut = 30.0f;
+    const p2r::Params P = params_of(&o);
+    const int def = default_variant(2);
+    float best = 1e30f, def_ms = -1.0f;
+    int best_i = -1;
+    for (size_t i = 0; i < vs.size(); ++i) {
+        if (vs[i].which != 2 || vs[i].learned || vs[i].fp64 || vs[i].upd2d) continue;
+        p2r::RaggedLaunch a{};
+        if ((rc = ragged_launch_args(ctx, vs[i], n, H, lmax, d_off, d_st, d_sv, d_hp, d_hc, d_par, d_cov, d_q, d_po,
+                                     d_co, d_c2, d_status, a))) {
+            cleanup();
+            return rc;
+        }
+        for (int w = 0; w < 2; ++w) TRY(p2r::launch_ragged(vs[i], a, P, s), "ragged launch");
+        TRY(hipEventRecord(e0, s), "hipEventRecord");
+        const int reps = 5;
+        for (int r = 0; r < reps; ++r) TRY(p2r::launch_ragged(vs[i], a, P, s), "ragged launch");
+        TRY(hipEventRecord(e1, s), "hipEventRecord");
+        TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.0f;
+        TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (ms < best) { best = ms; best_i = (int)i; }
+        if ((int)i == def) def_ms = ms;
+    }
+    cleanup();
+#undef TRY
+    if (best_i < 0) return fail(P2R_ENOTUNED, "no ragged variant");
+    if (def_ms > 0.0f && best >= 0.97f * def_ms) best_i = def;
+    ctx->chosen[2] = best_i;
+    ctx->cache[key] = vs[best_i].name;
+    save_cache(ctx);
+    return P2R_OK;
+}
+
 int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, void* stream) {
     if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
-    if (which < 0 || which > 1) return fail(P2R_EINVAL, "autotune supports which = 0 (p2r) or 1 (p2z)");
+    if (which < 0 || which > 2) return fail(P2R_EINVAL, "autotune supports which = 0 (p2r), 1 (p2z) or 2 (ragged)");
     if (n_tracks <= 0 || n_layers <= 0) return fail(P2R_EINVAL, "autotune needs n_tracks > 0 and n_layers > 0");
+    if (which == 2 && n_layers > 255) return fail(P2R_EINVAL, "ragged autotune: max_surfaces must be in [1, 255]");
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     const auto& vs = p2r::variants();
@@ -830,10 +965,11 @@ int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, vo
     if (it != ctx->cache.end()) {
         if (const p2r::Variant* v = find_variant(which, it->second)) {
             ctx->chosen[which] = (int)(v - vs.data());
-            return P2R_OK;
+            return which == 2 ? p2r_ctx_reserve(ctx, n_tracks, n_layers) : P2R_OK;
         }
     }
     hipStream_t s = (hipStream_t)stream;
+    if (which == 2) return autotune_ragged(ctx, key, n_tracks, n_layers, s);
     const size_t nb256 = ((size_t)n_tracks + 255) / 256;
     const size_t trk_sz = nb256 * 256 * 28, hit_sz = nb256 * 256 * 9 * (size_t)n_layers;
     float *surf = nullptr, *trk = nullptr, *hits = nullptr, *out = nullptr, *chi2 = nullptr;
@@ -851,12 +987,12 @@ int p2r_autotune(p2r_ctx* ctx, int which, int32_t n_tracks, int32_t n_layers, vo
             return hip_fail(e, what);             \
         }                                         \
     } while (0)
-    TRY(hipMalloc(&surf, sizeof(float) * n_layers), "hipMalloc");
-    TRY(hipMalloc(&trk, sizeof(float) * trk_sz), "hipMalloc");
-    TRY(hipMalloc(&hits, sizeof(float) * hit_sz), "hipMalloc");
-    TRY(hipMalloc(&out, sizeof(float) * trk_sz), "hipMalloc");
-    TRY(hipMalloc(&chi2, sizeof(float) * n_tracks), "hipMalloc");
-    TRY(hipMalloc(&st, sizeof(uint32_t) * n_tracks), "hipMalloc");
+    TRY(dev_alloc(&surf, sizeof(float) * n_layers), "hipMalloc");
+    TRY(dev_alloc(&trk, sizeof(float) * trk_sz), "hipMalloc");
+    TRY(dev_alloc(&hits, sizeof(float) * hit_sz), "hipMalloc");
+    TRY(dev_alloc(&out, sizeof(float) * trk_sz), "hipMalloc");
+    TRY(dev_alloc(&chi2, sizeof(float) * n_tracks), "hipMalloc");
+    TRY(dev_alloc(&st, sizeof(uint32_t) * n_tracks), "hipMalloc");
     hipEvent_t e0, e1;
     TRY(hipEventCreate(&e0), "hipEventCreate");
     TRY(hipEventCreate(&e1), "hipEventCreate");

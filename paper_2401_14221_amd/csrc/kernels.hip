@@ -28,6 +28,10 @@ __device__ __forceinline__ void store_track(float* __restrict__ t, int W, const 
     t[27 * W] = (float)st.q;
 }
 
+// Sums the lanes' helix evaluations into *evals.  Every lane of the wave
+// must reach this call (the cross-lane reduction reads all 64 lanes), so a
+// kernel that counts keeps its lanes past n in the loop, shadowing the last
+// track with a count of zero.
 __device__ __forceinline__ void count_evals(unsigned long long* evals, int iters) {
     if (!evals) return;
     unsigned long long v = (unsigned long long)iters;
@@ -50,7 +54,10 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
     }
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = gid < a.n;
-    if (!LEARNED && !active) return;
+    // lanes past n leave at once unless the wave must stay whole: the learned
+    // start evaluates the network over the whole wave, and the evaluation
+    // count is a reduction over all 64 lanes
+    if (!LEARNED && !active && !a.evals) return;
     const int g = active ? gid : a.n - 1;
     const int b = g / W, l = g % W;
     const float* tin = a.trk_in + (size_t)b * (28 * W) + l;
@@ -63,9 +70,11 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
     if (bad) flags = ST_BAD_INPUT;
     if (!bad || LEARNED) {
         const float* hb = a.hits + (size_t)b * ((size_t)a.L * 9 * W) + l;
-        float hm[9];
+        float hm[9] = {};
+        if (a.L > 0) {                    // with no layers there may be no hit buffer at all
 #pragma unroll
-        for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
+            for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
+        }
 #pragma unroll UNROLL
         for (int ly = 0; ly < a.L; ++ly) {
             const T m[3] = {hm[0], hm[1], hm[2]};
@@ -128,9 +137,11 @@ __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
         const T zsign = (float)st.p[5] < HALF_PI_F ? T(1) : T(-1);
         const size_t lstride = (size_t)nb * (9 * W);
         const float* hb = a.hits + (size_t)b * (9 * W) + l;
-        float hm[9];
+        float hm[9] = {};
+        if (a.L > 0) {                    // with no layers there may be no hit buffer at all
 #pragma unroll
-        for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
+            for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
+        }
 #pragma unroll UNROLL
         for (int ly = 0; ly < a.L; ++ly) {
             const T m[3] = {hm[0], hm[1], hm[2]};
@@ -222,11 +233,8 @@ P2Z_KERNEL(0, 2)
 #define VARD(WH, W, K) Variant{WH, W, 0, 1, #K, (const void*)&K, false, true, false}
 #define VAR2(W, F64, K) Variant{0, W, 0, 1, #K, (const void*)&K, false, F64, true}
 
-const void* ragged_grid_symbol(bool fp64, bool u2d);   // ragged.hip
-const void* ragged_fit_symbol(int wpe);
-
-const std::vector<Variant>& variants() {
-    static const std::vector<Variant> v = {
+static std::vector<Variant> make_variants() {
+    std::vector<Variant> v = {
         VAR(0, 64, 0, 1, p2r_w64_e0_u1),   // default p2r
         VAR(0, 32, 0, 1, p2r_w32_e0_u1),
         VAR(0, 128, 0, 1, p2r_w128_e0_u1),
@@ -240,13 +248,6 @@ const std::vector<Variant>& variants() {
         VAR(1, 64, 4, 1, p2z_w64_e4_u1),
         VAR(1, 64, 5, 1, p2z_w64_e5_u1),
         VAR(1, 64, 0, 2, p2z_w64_e0_u2),
-        // ragged: one workgroup per block (default), then the persistent work queue
-        Variant{2, RAG_W, 0, 1, "rag_fit_grid", ragged_grid_symbol(false, false), false, false, false, true},
-        Variant{2, RAG_W, 0, 1, "rag_fit_e0", ragged_fit_symbol(0), false, false, false},
-        Variant{2, RAG_W, 4, 1, "rag_fit_e4", ragged_fit_symbol(4), false, false, false},
-        Variant{2, RAG_W, 0, 1, "rag_fit_f64", ragged_grid_symbol(true, false), false, true, false, true},
-        Variant{2, RAG_W, 4, 1, "rag_fit_2d", ragged_grid_symbol(false, true), false, false, true, true},
-        Variant{2, RAG_W, 0, 1, "rag_fit_f64_2d", ragged_grid_symbol(true, true), false, true, true, true},
         VAR2(64, false, p2r_2d_w64),       // update in the hit frame
         VAR2(32, false, p2r_2d_w32),
         VAR2(128, false, p2r_2d_w128),
@@ -262,6 +263,12 @@ const std::vector<Variant>& variants() {
         VARL(256, 0, 1, p2r_mlp_w256_e0_u1),
         VARL(32, 0, 1, p2r_mlp_w32_e0_u1),
     };
+    append_ragged_variants(v);
+    return v;
+}
+
+const std::vector<Variant>& variants() {
+    static const std::vector<Variant> v = make_variants();
     return v;
 }
 
@@ -282,12 +289,6 @@ hipError_t launch_fit(const Variant& v, const FitLaunch& a, const Params& P, hip
 // |eta| in [1.7, 2.5] (p2z); the hits are the exact crossings of the
 // unsmeared track (surfaces evenly spaced in r = 2.5..110 cm or
 // |z| = 30..270 cm).
-__device__ __forceinline__ float hash_u01(uint32_t a, uint32_t b) {
-    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
-    h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
-    return (h >> 8) * (1.0f / 16777216.0f);
-}
-
 __global__ void synth_kernel(int which, int W, int32_t n, int32_t L, float* surf, float* trk, float* hits) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid < L) {

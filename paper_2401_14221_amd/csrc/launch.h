@@ -24,7 +24,16 @@ struct Variant {
     bool per_block = false;   // ragged: one workgroup per block instead of the persistent work queue
 };
 
+// Counter-hashed uniform in [0, 1) for the autotuner's synthetic tracks
+// (host and device compute the same values).
+__host__ __device__ __forceinline__ float hash_u01(uint32_t a, uint32_t b) {
+    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
+    return (h >> 8) * (1.0f / 16777216.0f);
+}
+
 const std::vector<Variant>& variants();
+void append_ragged_variants(std::vector<Variant>& v);   // ragged.hip
 
 struct FitLaunch {
     int32_t n, L;
@@ -41,12 +50,13 @@ struct FitLaunch {
 hipError_t launch_fit(const Variant& v, const FitLaunch& a, const Params& P, hipStream_t s);
 
 // Ragged path: tracks counting-sorted by (surface count descending, |eta|
-// bin), their hits packed per block of RAG_W sorted tracks into
-// [layer][RAG_FIELDS][RAG_W] rows, then the fit kernel over the blocks.
+// bin), then a fit kernel with one wave per block of RAG_W sorted tracks that
+// stages the block's hits through LDS.
 constexpr int RAG_W = 64;
 constexpr int RAG_ETA_BINS = 8;
 constexpr int RAG_FIELDS = 11;      // surface type, surface value, hit (3), hit covariance (6)
 constexpr int RAG_TPB = 1024;       // tracks per workgroup in the sort kernels
+constexpr int RAG_LSTRIDE = RAG_W + 1;  // floats per staged LDS row (one pad float)
 
 struct RaggedLaunch {
     int32_t n;                 // tracks
@@ -72,20 +82,25 @@ struct RaggedLaunch {
     int32_t* keys;             // [n] sort key of every track
     int64_t* run;              // [n] sorted position -> the track's first hit | surface count << 56
                                //     (RAG_RUN_SHIFT), or -1 for a track in the invalid bucket
-    int32_t* blk_off;          // [nb + 1] first packed layer row of each block
-    float* packed;             // [packed_cap][RAG_FIELDS][RAG_W] hits of the sorted blocks
-    int64_t packed_cap;        // layer rows available in packed
     int32_t nkeys;
     int32_t nb;                // blocks of RAG_W sorted tracks
     int32_t grid;              // workgroups of the persistent variant (one wave each)
 };
 
-// Layer rows the packed hits of n tracks with n_hits surfaces in total can
-// need when the CSR ranges do not overlap (blocks that would not fit are
-// reported as BAD_INPUT by the fit).
-int64_t ragged_packed_rows(int64_t n_hits, int lmax);
 constexpr int RAG_RUN_SHIFT = 56;
 int ragged_nkeys(int lmax);
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s);
+
+// Autotuner input for the ragged fit: the surface count of synthetic track t
+// (5 .. lmax, or lmax when lmax < 5), and a kernel that fills each track's
+// start (the origin, initial covariance of the fit workloads) and its CSR
+// run of surfaces and exact hits.
+__host__ __device__ __forceinline__ int ragged_synth_count(int32_t t, int lmax) {
+    if (lmax < 5) return lmax;
+    const int L = 5 + (int)(hash_u01((uint32_t)t, 11) * (float)(lmax - 4));
+    return L > lmax ? lmax : L;
+}
+hipError_t launch_ragged_synth(int32_t n, int lmax, const int64_t* offsets, uint8_t* stype, float* sval,
+                               float* hpos, float* hcov, float* par, float* cov, int8_t* q, hipStream_t s);
 
 }  // namespace p2r

@@ -5,38 +5,28 @@
 //   1. rag_reset   zero the key histogram and the work-queue counter
 //   2. rag_hist    sort key of every track; per-workgroup histogram in LDS,
 //                  then one global atomic per (workgroup, key)
-//   3. rag_scan    (one workgroup) bucket starts, and for every block of
-//                  RAG_W sorted tracks its first packed layer row
+//   3. rag_scan    (one workgroup) the first sorted position of every key
 //   4. rag_scatter counting-sort scatter -> perm[sorted position] = track and
 //                  run[sorted position] = its CSR run, ranks from LDS
 //                  atomics, one cursor atomic per (workgroup, key)
-//   5. rag_pack    one workgroup per block: copies its tracks' hits from the
-//                  CSR arrays (coalesced reads of each track's run) through
-//                  an LDS tile into [layer][RAG_FIELDS][RAG_W] rows
-//   6. rag_fit_grid one wave per block, in block order: streams the block's
-//                  packed rows (next layer prefetched) and fits its 64
-//                  tracks (rag_fit: the same with a persistent grid whose
-//                  waves take blocks from an atomic counter)
+//   5. rag_fit_*   one wave per block of RAG_W sorted tracks: streams the
+//                  block's hits from the CSR arrays through LDS, a chunk of
+//                  surfaces at a time, and fits its 64 tracks (the queue
+//                  variant: a persistent grid whose waves take blocks from an
+//                  atomic counter)
 // The key orders tracks by surface count (longest first, so the longest
 // blocks start first and the tail of the work is short blocks) and then by a
 // |eta| bin, so the 64 lanes of a wave see similar surface sequences and
 // branch the same way between cylinders and planes.  Gathering the hits
-// lane by lane (each lane walking its own track's run) evicts each lane's
-// cache lines before their next use, at 10-20x the algorithmic traffic; the
-// pack pass reads every run with consecutive lanes instead.
+// lane by lane (each lane walking its own track's run) would evict each
+// lane's cache lines before their next use; the staged copy reads the runs
+// with consecutive lanes instead.
 #include "launch.h"
 #include "track_math.h"
 
 namespace p2r {
 
 int ragged_nkeys(int lmax) { return (lmax + 1) * RAG_ETA_BINS + 1; }
-
-int64_t ragged_packed_rows(int64_t n_hits, int lmax) {
-    // sum over blocks of the block's (largest) surface count: a block inside
-    // one key bucket holds RAG_W tracks of equal count; the last block and
-    // each block that straddles a bucket boundary add at most lmax
-    return (n_hits + RAG_W - 1) / RAG_W + (int64_t)lmax * ragged_nkeys(lmax) + 1;
-}
 
 __device__ __forceinline__ int track_key(const RaggedLaunch& a, int64_t t) {
     const int64_t h0 = a.offsets[t];
@@ -81,73 +71,28 @@ __global__ void __launch_bounds__(256) rag_hist(RaggedLaunch a) {
         if (lh[k]) atomicAdd(&a.hist[k], lh[k]);
 }
 
-// One workgroup of 1024 threads.  dynamic LDS: nkeys bucket starts.
-//   base[k]    = sum of hist[k'] for k' < k
-//   blk_off[b] = sum of Lb' for b' < b, Lb = surface count of the key bucket
-//                holding the block's first sorted position (its largest,
-//                since counts decrease along the sorted order); a block whose
-//                rows would pass packed_cap gets none (its tracks are then
-//                reported BAD_INPUT by the fit).
+// One workgroup of 1024 threads: base[k] = sum of hist[k'] for k' < k.
 __global__ void __launch_bounds__(1024) rag_scan(RaggedLaunch a) {
     __shared__ int32_t part[1024];
-    extern __shared__ int32_t sbase[];
     const int tid = threadIdx.x;
-    {
-        const int per = (a.nkeys + 1023) / 1024;
-        const int lo = min(tid * per, a.nkeys), hi = min(lo + per, a.nkeys);
-        int32_t s = 0;
-        for (int i = lo; i < hi; ++i) s += a.hist[i];
-        part[tid] = s;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int32_t v = tid >= off ? part[tid - off] : 0;
-            __syncthreads();
-            part[tid] += v;
-            __syncthreads();
-        }
-        int32_t run = tid > 0 ? part[tid - 1] : 0;
-        for (int i = lo; i < hi; ++i) {
-            const int32_t c = a.hist[i];
-            a.base[i] = run;
-            sbase[i] = run;
-            run += c;
-        }
-    }
-    __syncthreads();
-    // rows of block b: the bucket of position 64 b is the largest k with
-    // sbase[k] <= 64 b (an empty bucket shares its start with the next one)
-    auto rows_of = [&](int b) -> int {
-        const int32_t pos = b * RAG_W;
-        int lo = 0, hi = a.nkeys - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sbase[mid] <= pos) lo = mid; else hi = mid - 1;
-        }
-        return key_layers(a, lo);
-    };
-    const int per = (a.nb + 1023) / 1024;
-    const int lo = min(tid * per, a.nb), hi = min(lo + per, a.nb);
-    int64_t s = 0;
-    for (int b = lo; b < hi; ++b) s += rows_of(b);
-    __syncthreads();
-    __shared__ int64_t part64[1024];
-    part64[tid] = s;
+    const int per = (a.nkeys + 1023) / 1024;
+    const int lo = min(tid * per, a.nkeys), hi = min(lo + per, a.nkeys);
+    int32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += a.hist[i];
+    part[tid] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t v = tid >= off ? part64[tid - off] : 0;
+        const int32_t v = tid >= off ? part[tid - off] : 0;
         __syncthreads();
-        part64[tid] += v;
+        part[tid] += v;
         __syncthreads();
     }
-    int64_t run = tid > 0 ? part64[tid - 1] : 0;
-    const int64_t cap = a.packed_cap;
-    for (int b = lo; b < hi; ++b) {
-        const int r = rows_of(b);
-        const int64_t start = run < cap ? run : cap;
-        a.blk_off[b] = (int32_t)start;
-        run += r;
+    int32_t run = tid > 0 ? part[tid - 1] : 0;
+    for (int i = lo; i < hi; ++i) {
+        const int32_t c = a.hist[i];
+        a.base[i] = run;
+        run += c;
     }
-    if (tid == 1023) a.blk_off[a.nb] = (int32_t)(run < cap ? run : cap);
 }
 
 // dynamic LDS: 2 nkeys ints (ranks, workgroup bases)
@@ -179,147 +124,181 @@ __global__ void __launch_bounds__(256) rag_scatter(RaggedLaunch a) {
         if (key[j] >= 0) {
             const int32_t pos = off[key[j]] + rank[j];
             a.perm[pos] = (int32_t)t;
-            // the track's CSR run in sorted order, so that the pack and the
-            // fit read it sequentially instead of gathering offsets[t]
+            // the track's CSR run in sorted order, so that the fit reads it
+            // sequentially instead of gathering offsets[t]
             const int L = key_layers(a, key[j]);
             a.run[pos] = key[j] < a.nkeys - 1 ? (a.offsets[t] | ((int64_t)L << RAG_RUN_SHIFT)) : (int64_t)-1;
         }
     }
 }
 
-// One workgroup of 256 threads per block of RAG_W sorted tracks.  Row j of
-// the block holds, for field f and the track at sorted position 64 b + l,
-// packed[((blk_off[b] + j) RAG_FIELDS + f) RAG_W + l].  The rows are built in
-// LDS tiles of up to PACK_ROWS rows for PACK_TRACKS tracks.  Filling a tile,
-// the workgroup's threads cover each CSR array's runs of the tile's tracks
-// with consecutive threads on consecutive elements (whole runs, so every
-// fetched cache line is used), and each thread issues all of its loads
-// (about 17) before it stores any of them, so that enough reads are in
-// flight to cover the memory latency.  The tile is track-major with an odd
-// track stride: the fill's stores and the drain's loads are free of bank
-// conflicts.  It then goes out as 64-byte pieces of the block's rows, which
-// the L2 merges into whole lines.  Tile entries of a track with fewer rows
-// keep stale values, which the fit never reads (it stops at the track's
-// count).
-constexpr int PACK_ROWS = 24;
-constexpr int PACK_TRACKS = 16;
-constexpr int PACK_TSTRIDE = PACK_ROWS * RAG_FIELDS + 1;
-constexpr int PACK_THREADS = 256;
+// ------------------------------------------------------------ the fit
+// One wave fits the RAG_W tracks at sorted positions RAG_W b .. RAG_W b + 63,
+// lane l the track at RAG_W b + l.  The wave streams the tracks' hits through
+// LDS: it copies a chunk of surfaces of its 64 tracks from the CSR arrays
+// into rows [surface][field][lane], then each lane reads its own hits from
+// there.  The copy is coalesced: for each CSR array the 64 tracks' runs of
+// the chunk's surfaces are read by consecutive lanes on consecutive
+// elements, so a load instruction touches a few cache lines instead of 64.
+// A cache line that holds the end of one chunk of a track and the start of
+// its next is evicted from L2 before the next chunk is read (the wave's next
+// chunk comes tens of microseconds later), so every chunk read costs about
+// one extra line per array and track.  The small arrays (surface type and
+// value, 5 B per surface) are therefore read in chunks of CB surfaces, the
+// hit position and covariance (36 B per surface) in chunks of C, which is
+// what bounds the LDS a wave needs.  Every load of a chunk is issued before
+// any is stored (PREFETCH: the next chunk's loads are issued before the
+// current chunk is fitted, and stored after it).  Tracks are sorted by
+// surface count, longest first, so the block's first track has the most
+// surfaces and a wave needs as many chunks as that track.
 
-__global__ void __launch_bounds__(PACK_THREADS) rag_pack(RaggedLaunch a) {
-    __shared__ float tile[PACK_TRACKS * PACK_TSTRIDE];
-    __shared__ int32_t s_rows[RAG_W];
-    __shared__ int64_t s_h0[RAG_W];
-    const int b = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int64_t o = a.blk_off[b];
-    const int rows = a.blk_off[b + 1] - (int32_t)o;
-    if (tid < RAG_W) {
-        const int64_t p = (int64_t)b * RAG_W + tid;
-        int L = 0;
-        int64_t h0 = 0;
-        if (p < a.n) {
-            const int64_t r = a.run[p];
-            if (r >= 0) {                                // -1: invalid CSR range, no rows
-                L = min((int)(r >> RAG_RUN_SHIFT), rows);
-                h0 = r & (((int64_t)1 << RAG_RUN_SHIFT) - 1);
+constexpr int RAG_HIT_FIELDS = 9;      // hit position (3) and covariance (6)
+
+// Staging area of one wave: the rows of the current chunks, and each lane's
+// CSR run (first hit, surface count; count 0 for a track that is not fitted).
+template <int C, int CB>
+struct RagStage {
+    float hit[C * RAG_HIT_FIELDS * RAG_LSTRIDE];   // [j][field][lane], surfaces k0 .. k0 + C - 1
+    float sval[CB * RAG_LSTRIDE];                  // [j][lane], surfaces kb .. kb + CB - 1
+    uint8_t stype[CB * RAG_W];                     // [j][lane]
+    uint2 run[RAG_W];
+};
+
+// Which element of a chunk of K surfaces each lane copies.  Lane l serves
+// the tracks tt = g (64 / K) + l / K, g = 0 .. K - 1, as sub-lane u = l % K
+// of each: of a track's K E units in an array with E units per surface (the
+// run of its surfaces k0 .. k0 + K - 1), sub-lane u takes units u, u + K,
+// ..., u + (E - 1) K, so the K sub-lanes of a track read consecutive units
+// and a load instruction covers 64 / K tracks.  A unit past the track's last
+// surface is not copied: its slot loads unit 0 of the array (which exists
+// whenever any track has a surface) and stores nothing.
+template <int K>
+struct Lanes {
+    uint32_t h0[K];    // CSR index of surface k0 of each served track
+    int cnt[K];        // its surfaces left from k0 on
+    int tt[K];         // its lane in the block
+    int u;             // sub-lane
+};
+
+template <int K>
+__device__ __forceinline__ Lanes<K> lanes_of(const uint2* run, int lane, int k0) {
+    Lanes<K> q;
+    q.u = lane % K;
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+        q.tt[g] = g * (RAG_W / K) + lane / K;
+        const uint2 r = run[q.tt[g]];
+        q.h0[g] = r.x + (uint32_t)k0;
+        q.cnt[g] = (int)r.y - k0;
+    }
+    return q;
+}
+
+// unit m (0 .. E - 1) of sub-lane u for served track g: surface j of the
+// chunk, and the unit's index in its array (0 when it is past the run)
+template <int K, int E>
+__device__ __forceinline__ uint32_t unit_src(const Lanes<K>& q, int g, int m, int& j, bool& ok) {
+    const int unit = q.u + K * m;
+    j = unit / E;
+    ok = j < q.cnt[g];
+    return ok ? q.h0[g] * E + (uint32_t)unit : 0u;
+}
+
+// Loads of one chunk, held in registers between issue and store.
+template <int C>
+struct HitRegs {
+    float p[3 * C];         // hit position, one float per slot
+    float2 c[3 * C];        // hit covariance, two floats per slot
+};
+template <int CB>
+struct SurfRegs {
+    uint32_t t[CB];         // surface type byte
+    float v[CB];            // surface value
+};
+
+// The slot arithmetic depends only on the lane and the chunk, so the
+// compiler would hoist it out of the chunk loop and keep ~2 registers per
+// slot alive through the whole fit; a lane index it cannot see through keeps
+// it where it is used.
+__device__ __forceinline__ int opaque_lane(int lane) {
+    asm volatile("" : "+v"(lane));
+    return lane;
+}
+
+// Element i of an array at a 32-bit byte offset from its base (the call
+// checks that every CSR array stays below 4 GiB), so that each load needs one
+// offset register rather than a 64-bit address.
+template <typename V>
+__device__ __forceinline__ V load_at(const void* base, uint32_t i) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(V));
+}
+
+template <int C>
+__device__ __forceinline__ void hit_load(const RaggedLaunch& a, const uint2* run, int lane, int k0, HitRegs<C>& R) {
+    const Lanes<C> q = lanes_of<C>(run, opaque_lane(lane), k0);
+    int j;
+    bool ok;
+#pragma unroll
+    for (int g = 0; g < C; ++g)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            R.p[3 * g + m] = load_at<float>(a.hpos, unit_src<C, 3>(q, g, m, j, ok));
+            R.c[3 * g + m] = load_at<float2>(a.hcov, unit_src<C, 3>(q, g, m, j, ok));
+        }
+}
+
+template <int C, int CB>
+__device__ __forceinline__ void hit_store(RagStage<C, CB>& S, int lane, int k0, const HitRegs<C>& R) {
+    const Lanes<C> q = lanes_of<C>(S.run, opaque_lane(lane), k0);
+    int j;
+    bool ok;
+#pragma unroll
+    for (int g = 0; g < C; ++g)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            (void)unit_src<C, 3>(q, g, m, j, ok);
+            const int e = q.u + C * m - 3 * j;          // position / covariance pair within the surface
+            if (ok) {
+                float* row = S.hit + j * (RAG_HIT_FIELDS * RAG_LSTRIDE) + q.tt[g];
+                row[e * RAG_LSTRIDE] = R.p[3 * g + m];
+                row[(3 + 2 * e) * RAG_LSTRIDE] = R.c[3 * g + m].x;
+                row[(4 + 2 * e) * RAG_LSTRIDE] = R.c[3 * g + m].y;
             }
         }
-        s_rows[tid] = L;
-        s_h0[tid] = h0;
+}
+
+template <int CB>
+__device__ __forceinline__ void surf_load(const RaggedLaunch& a, const uint2* run, int lane, int k0, SurfRegs<CB>& R) {
+    const Lanes<CB> q = lanes_of<CB>(run, opaque_lane(lane), k0);
+    int j;
+    bool ok;
+#pragma unroll
+    for (int g = 0; g < CB; ++g) {
+        R.t[g] = load_at<uint8_t>(a.stype, unit_src<CB, 1>(q, g, 0, j, ok));
+        R.v[g] = load_at<float>(a.sval, unit_src<CB, 1>(q, g, 0, j, ok));
     }
-    __syncthreads();
-    // per-track element counts of a full tile, and each thread's slots
-    constexpr int NCOV = 6 * PACK_ROWS, NPOS = 3 * PACK_ROWS, NSUR = PACK_ROWS;
-    constexpr int SC = (PACK_TRACKS * NCOV + PACK_THREADS - 1) / PACK_THREADS;
-    constexpr int SP = (PACK_TRACKS * NPOS + PACK_THREADS - 1) / PACK_THREADS;
-    constexpr int SS = (PACK_TRACKS * NSUR + PACK_THREADS - 1) / PACK_THREADS;
-    float* dst = a.packed + (size_t)o * (RAG_FIELDS * RAG_W);
-    __shared__ int32_t t_rows[PACK_TRACKS];              // rows of each tile track (<= 0: none)
-    __shared__ int64_t t_h[PACK_TRACKS];                 // and its first hit in the tile
-    for (int c0 = 0; c0 < rows; c0 += PACK_ROWS) {
-        const int nr = min(PACK_ROWS, rows - c0);
-        // The block's first track has the most rows (counts fall along the
-        // sorted order), rows of them, so its hit c0 exists: slots that have
-        // no element of their own load that one, which keeps every load
-        // unconditional, and do not store it.
-        const int64_t hsafe = s_h0[0] + c0;
-        for (int k0 = 0; k0 < RAG_W; k0 += PACK_TRACKS) {
-            if (tid < PACK_TRACKS) {
-                t_rows[tid] = min(nr, s_rows[k0 + tid] - c0);
-                t_h[tid] = s_h0[k0 + tid] + c0;
-            }
-            __syncthreads();
-            // element index of every slot in its array (the safe one when idle)
-            int64_t ic[SC], ip[SP], is[SS];
-            bool okc[SC], okp[SP], oks[SS];
+}
+
+template <int C, int CB>
+__device__ __forceinline__ void surf_store(RagStage<C, CB>& S, int lane, int k0, const SurfRegs<CB>& R) {
+    const Lanes<CB> q = lanes_of<CB>(S.run, opaque_lane(lane), k0);
+    int j;
+    bool ok;
 #pragma unroll
-            for (int i = 0; i < SC; ++i) {
-                const int slot = tid + PACK_THREADS * i, kt = min(slot / NCOV, PACK_TRACKS - 1), e = slot - kt * NCOV;
-                okc[i] = slot < PACK_TRACKS * NCOV && e < 6 * t_rows[kt];
-                ic[i] = okc[i] ? t_h[kt] * 6 + e : hsafe * 6;
-            }
-#pragma unroll
-            for (int i = 0; i < SP; ++i) {
-                const int slot = tid + PACK_THREADS * i, kt = min(slot / NPOS, PACK_TRACKS - 1), e = slot - kt * NPOS;
-                okp[i] = slot < PACK_TRACKS * NPOS && e < 3 * t_rows[kt];
-                ip[i] = okp[i] ? t_h[kt] * 3 + e : hsafe * 3;
-            }
-#pragma unroll
-            for (int i = 0; i < SS; ++i) {
-                const int slot = tid + PACK_THREADS * i, kt = min(slot / NSUR, PACK_TRACKS - 1), e = slot - kt * NSUR;
-                oks[i] = slot < PACK_TRACKS * NSUR && e < t_rows[kt];
-                is[i] = oks[i] ? t_h[kt] + e : hsafe;
-            }
-            float vc[SC], vp[SP], vs[SS], vt[SS];
-#pragma unroll
-            for (int i = 0; i < SC; ++i) vc[i] = a.hcov[ic[i]];
-#pragma unroll
-            for (int i = 0; i < SP; ++i) vp[i] = a.hpos[ip[i]];
-#pragma unroll
-            for (int i = 0; i < SS; ++i) {
-                vs[i] = a.sval[is[i]];
-                vt[i] = (float)a.stype[is[i]];
-            }
-#pragma unroll
-            for (int i = 0; i < SC; ++i) {
-                const int slot = tid + PACK_THREADS * i, kt = slot / NCOV, e = slot - kt * NCOV;
-                if (okc[i]) tile[kt * PACK_TSTRIDE + (e / 6) * RAG_FIELDS + 5 + e % 6] = vc[i];
-            }
-#pragma unroll
-            for (int i = 0; i < SP; ++i) {
-                const int slot = tid + PACK_THREADS * i, kt = slot / NPOS, e = slot - kt * NPOS;
-                if (okp[i]) tile[kt * PACK_TSTRIDE + (e / 3) * RAG_FIELDS + 2 + e % 3] = vp[i];
-            }
-#pragma unroll
-            for (int i = 0; i < SS; ++i) {
-                const int slot = tid + PACK_THREADS * i, kt = slot / NSUR, e = slot - kt * NSUR;
-                if (oks[i]) {
-                    tile[kt * PACK_TSTRIDE + e * RAG_FIELDS + 1] = vs[i];
-                    tile[kt * PACK_TSTRIDE + e * RAG_FIELDS] = vt[i];
-                }
-            }
-            __syncthreads();
-            float* d = dst + (size_t)c0 * (RAG_FIELDS * RAG_W) + k0;
-            for (int e = tid; e < nr * RAG_FIELDS * PACK_TRACKS; e += PACK_THREADS) {
-                const int rf = e / PACK_TRACKS, kt = e % PACK_TRACKS;   // rf = row * RAG_FIELDS + field
-                d[(size_t)rf * RAG_W + kt] = tile[kt * PACK_TSTRIDE + rf];
-            }
-            __syncthreads();
+    for (int g = 0; g < CB; ++g) {
+        (void)unit_src<CB, 1>(q, g, 0, j, ok);
+        if (ok) {
+            S.stype[j * RAG_W + q.tt[g]] = (uint8_t)R.t[g];
+            S.sval[j * RAG_LSTRIDE + q.tt[g]] = R.v[g];
         }
     }
 }
 
-// Fits the track at sorted position RAG_W b + lane (b uniform over the
-// wave).  Every load the block needs first (its rows, the track record, the
-// first packed row) is issued before any is used, so the block start costs
-// one memory round trip after the perm/run reads.
-template <typename T, bool U2D>
-__device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Params& P, int b, int lane) {
+template <int C, int CB, bool PREFETCH, typename T, bool U2D>
+__device__ __forceinline__ void fit_block(const RaggedLaunch& a, const Params& P, RagStage<C, CB>& S, int b, int lane) {
+    static_assert(CB % C == 0 && RAG_W % CB == 0 && RAG_W % C == 0, "chunk sizes");
     const int64_t p = (int64_t)b * RAG_W + lane;
     const bool live = p < a.n;                    // lane 0 always is
-    const int64_t o = a.blk_off[b];
-    const int rows = a.blk_off[b + 1] - (int32_t)o;
     // run[p]: the surface count of a track whose CSR range the sort found
     // valid (0 <= L <= lmax, inside [0, n_hits)); -1 for every other track.
     // A lane past the last track reads the last track's entries, which it
@@ -334,51 +313,68 @@ __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Pa
     for (int f = 0; f < 21; ++f) st.c[f] = a.cov_in[(size_t)t * 21 + f];
     const int qi = a.q[t];
     st.q = (T)qi;
-    const float* src = a.packed + (size_t)o * (RAG_FIELDS * RAG_W) + lane;
-    float hb[RAG_FIELDS];
-    if (rows > 0) {
-#pragma unroll
-        for (int f = 0; f < RAG_FIELDS; ++f) hb[f] = src[f * RAG_W];
-    }
-    if (!live) return;
     const int L = r < 0 ? 0 : (int)(r >> RAG_RUN_SHIFT);
-    uint32_t flags = 0;
+    const bool bad = (r < 0) | ((qi != 1) & (qi != -1)) | bad_input(st);
+    // the previous block's wave may still read the staging area
+    __syncthreads();
+    S.run[lane] = make_uint2((uint32_t)(r & (((int64_t)1 << RAG_RUN_SHIFT) - 1)), bad ? 0u : (uint32_t)L);
+    // surfaces to stage: the block's first track has the most
+    const int rows = __builtin_amdgcn_readfirstlane(L);
+    uint32_t flags = bad ? ST_BAD_INPUT : 0u;
     int nused = 0;
     T chi2 = 0;
-    const bool bad = (r < 0) | (L > rows) | ((qi != 1) & (qi != -1)) | bad_input(st);
-    if (bad) {
-        flags = ST_BAD_INPUT;
-    } else {
-        for (int j = 0; j < (int)L; ++j) {
-            const float type = hb[0];
-            const T v = hb[1];
-            const T m[3] = {hb[2], hb[3], hb[4]};
-            const T V[6] = {hb[5], hb[6], hb[7], hb[8], hb[9], hb[10]};
-            if (j + 1 < (int)L) {
-                const float* nx = src + (size_t)(j + 1) * (RAG_FIELDS * RAG_W);
+    HitRegs<C> RH;
+    __syncthreads();
+    if (rows > 0) hit_load<C>(a, S.run, lane, 0, RH);
+    for (int k0 = 0; k0 < rows; k0 += C) {
+        const int kb = k0 % CB;                 // this chunk's first row in the CB rows
+        __syncthreads();                        // lanes are done reading the previous chunk
+        hit_store<C, CB>(S, lane, k0, RH);
+        if (kb == 0) {
+            // the surface types and values of CB surfaces, loaded and stored
+            // at once (after the hit registers are free) so that their
+            // registers are free during the fit; the wait is taken once
+            // every CB surfaces
+            SurfRegs<CB> RS;
+            surf_load<CB>(a, S.run, lane, k0, RS);
+            surf_store<C, CB>(S, lane, k0, RS);
+        }
+        __syncthreads();
+        const int k1 = k0 + C;
+        if (PREFETCH && k1 < rows) hit_load<C>(a, S.run, lane, k1, RH);
+        const int nj = bad ? 0 : min(C, L - k0);
+#pragma unroll 1
+        for (int j = 0; j < nj; ++j) {
+            const float* row = S.hit + j * (RAG_HIT_FIELDS * RAG_LSTRIDE) + lane;
+            float hb[RAG_HIT_FIELDS];
 #pragma unroll
-                for (int f = 0; f < RAG_FIELDS; ++f) hb[f] = nx[f * RAG_W];
-            }
+            for (int f = 0; f < RAG_HIT_FIELDS; ++f) hb[f] = row[f * RAG_LSTRIDE];
+            const int type = S.stype[(kb + j) * RAG_W + lane];
+            const T v = S.sval[(kb + j) * RAG_LSTRIDE + lane];
+            const T m[3] = {hb[0], hb[1], hb[2]};
+            const T V[6] = {hb[3], hb[4], hb[5], hb[6], hb[7], hb[8]};
             T c2 = 0;
             StepOut out{0u, false, 0};
             if constexpr (U2D) {
                 // cylinders and planes take different updates
-                if (type == 0.0f) out = step_cylinder<T, true>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
-                else if (type == 1.0f) out = step_plane<T>(st, v, m, V, P, c2);
+                if (type == 0) out = step_cylinder<T, true>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
+                else if (type == 1) out = step_plane<T>(st, v, m, V, P, c2);
                 else out.flags = ST_BAD_INPUT;
             } else {
                 // Lanes of one wave may meet cylinders and planes in the same
                 // row: the two propagations diverge, and the update after them
                 // is shared, so such a row costs one update, not two.
-                if (type == 0.0f) out = step_cylinder<T, false, false>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
-                else if (type == 1.0f) out = step_plane<T, false>(st, v, m, V, P, c2);
+                if (type == 0) out = step_cylinder<T, false, false>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
+                else if (type == 1) out = step_plane<T, false>(st, v, m, V, P, c2);
                 else out.flags = ST_BAD_INPUT;
                 if (out.updated) update_step<T>(st, m, V, P, c2, out);
             }
             flags |= out.flags;
             if (out.updated) { ++nused; chi2 += c2; }
         }
+        if (!PREFETCH && k1 < rows) hit_load<C>(a, S.run, lane, k1, RH);
     }
+    if (!live) return;
 #pragma unroll
     for (int f = 0; f < 6; ++f) a.par_out[(size_t)t * 6 + f] = (float)st.p[f];
 #pragma unroll
@@ -387,48 +383,140 @@ __device__ __forceinline__ void fit_sorted_track(const RaggedLaunch& a, const Pa
     a.status[t] = flags | ST_DONE | ((uint32_t)(nused > 255 ? 255 : nused) << NUSED_SHIFT);
 }
 
-// The fit, one workgroup (one wave) per block of RAG_W sorted tracks: the
-// dispatcher hands the blocks out in order, longest first, and refills each
-// slot as its wave ends.  (Faster here than the persistent work queue below:
-// 0.96 against 1.07 ms for the 10^6-track ragged workload.)
-template <int WPE, typename T, bool U2D>
+// One workgroup (one wave) per block: the dispatcher hands the blocks out in
+// order, longest first, and refills each slot as its wave ends.
+template <int C, int CB, bool PREFETCH, int WPE, typename T, bool U2D>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 rag_fit_grid(RaggedLaunch a, Params P) {
-    fit_sorted_track<T, U2D>(a, P, blockIdx.x, threadIdx.x);
+    __shared__ RagStage<C, CB> S;
+    fit_block<C, CB, PREFETCH, T, U2D>(a, P, S, blockIdx.x, threadIdx.x);
 }
 
 // The persistent variant: a grid of resident waves takes blocks from an
 // atomic counter.  Every wave leaves the loop once the counter passes the
 // last block, so the grid drains whatever its size.
-template <int WPE, typename T, bool U2D>
+template <int C, int CB, bool PREFETCH, int WPE, typename T, bool U2D>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
-rag_fit(RaggedLaunch a, Params P) {
+rag_fit_queue(RaggedLaunch a, Params P) {
+    __shared__ RagStage<C, CB> S;
     const int lane = threadIdx.x;
     while (true) {
         int b = 0;
         if (lane == 0) b = atomicAdd(a.work, 1);
         b = __builtin_amdgcn_readfirstlane(b);
         if (b >= a.nb) break;
-        fit_sorted_track<T, U2D>(a, P, b, lane);
+        fit_block<C, CB, PREFETCH, T, U2D>(a, P, S, b, lane);
     }
 }
 
-template __global__ void rag_fit_grid<0, float, false>(RaggedLaunch, Params);
-template __global__ void rag_fit_grid<2, double, false>(RaggedLaunch, Params);
-template __global__ void rag_fit_grid<4, float, true>(RaggedLaunch, Params);
-template __global__ void rag_fit_grid<2, double, true>(RaggedLaunch, Params);
-template __global__ void rag_fit<0, float, false>(RaggedLaunch, Params);
-template __global__ void rag_fit<4, float, false>(RaggedLaunch, Params);
+#define RAG_GRID(C, CB, PF, WPE, T, U2D) (const void*)&rag_fit_grid<C, CB, PF, WPE, T, U2D>
+#define RAG_QUEUE(C, CB, PF, WPE) (const void*)&rag_fit_queue<C, CB, PF, WPE, float, false>
 
-// FP32 at occupancy target wpe (0 or 4), or FP64; the 3D update or the one
-// in the hit frame on cylinders (128 VGPRs, spilling only at the FP64 calls)
-const void* ragged_grid_symbol(bool fp64, bool u2d) {
-    if (fp64) return u2d ? (const void*)&rag_fit_grid<2, double, true> : (const void*)&rag_fit_grid<2, double, false>;
-    return u2d ? (const void*)&rag_fit_grid<4, float, true> : (const void*)&rag_fit_grid<0, float, false>;
+// which, width, waves/EU, unroll (here: surfaces per staged hit chunk), name,
+// kernel, learned, fp64, 2D update, one workgroup per block.  Names: c<C>
+// surfaces per hit chunk, b<CB> per surface-type/value chunk, pf prefetch,
+// e<N> compiled for N waves per SIMD, queue the persistent grid.
+void append_ragged_variants(std::vector<Variant>& v) {
+    // the first is the default (the fastest measured on the 10^6-track workload)
+    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b16_pf", RAG_GRID(4, 16, true, 0, float, false), false, false, false, true});
+    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b16", RAG_GRID(4, 16, false, 0, float, false), false, false, false, true});
+    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b8", RAG_GRID(4, 8, false, 0, float, false), false, false, false, true});
+    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b4", RAG_GRID(4, 4, false, 0, float, false), false, false, false, true});
+    v.push_back(Variant{2, RAG_W, 0, 8, "rag_fit_c8b16", RAG_GRID(8, 16, false, 0, float, false), false, false, false, true});
+    v.push_back(Variant{2, RAG_W, 4, 4, "rag_fit_c4b16_e4", RAG_GRID(4, 16, false, 4, float, false), false, false, false, true});
+    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b16_queue", RAG_QUEUE(4, 16, false, 0), false, false, false, false});
+    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_f64", RAG_GRID(4, 16, false, 2, double, false), false, true, false, true});
+    v.push_back(Variant{2, RAG_W, 4, 4, "rag_fit_2d", RAG_GRID(4, 16, false, 4, float, true), false, false, true, true});
+    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_f64_2d", RAG_GRID(4, 16, false, 2, double, true), false, true, true, true});
 }
 
-const void* ragged_fit_symbol(int wpe) {
-    return wpe == 4 ? (const void*)&rag_fit<4, float, false> : (const void*)&rag_fit<0, float, false>;
+// ------------------------------------------------------ autotuner input
+// Synthetic ragged tracks: pT in [0.5, 10] GeV, eta in [-2.5, 2.5], phi
+// uniform, from the origin; surfaces in crossing order among cylinders at
+// r = 2.5 .. 110 cm and disks at |z| = 30 .. 270 cm (25 of each, on the
+// track's side in z), the next one being whichever of the next cylinder and
+// the next disk the helix reaches first.  Hits are the exact crossings with
+// the fit workloads' hit covariance; slots past the point where the track
+// leaves the volume (or needs more than half a turn) get a NaN hit, which
+// the fit skips (HIT_MISSING).
+__global__ void rag_synth(int32_t n, int lmax, const int64_t* offsets, uint8_t* stype, float* sval, float* hpos,
+                          float* hcov, float* par, float* cov, int8_t* q) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float pt = 0.5f + 9.5f * hash_u01(t, 1);
+    const float eta = -2.5f + 5.0f * hash_u01(t, 2);
+    const float phi0 = -PI_F + TWO_PI_F * hash_u01(t, 3);
+    const float qq = hash_u01(t, 4) < 0.5f ? -1.0f : 1.0f;
+    const float th = 2.0f * atanf(expf(-eta));
+    const float p6[6] = {0.0f, 0.0f, 0.0f, 1.0f / pt, phi0, th};
+    for (int f = 0; f < 6; ++f) par[(size_t)t * 6 + f] = p6[f];
+    for (int k = 0; k < 21; ++k) cov[(size_t)t * 21 + k] = 0.0f;
+    cov[(size_t)t * 21 + I21(0, 0)] = 0.01f; cov[(size_t)t * 21 + I21(1, 1)] = 0.01f;
+    cov[(size_t)t * 21 + I21(2, 2)] = 1.0f; cov[(size_t)t * 21 + I21(3, 3)] = 1e-4f;
+    cov[(size_t)t * 21 + I21(4, 4)] = 1e-4f; cov[(size_t)t * 21 + I21(5, 5)] = 1e-4f;
+    q[t] = qq > 0.0f ? 1 : -1;
+    const float w = -qq * KAPPA * 3.8f / pt;
+    const float cot = cosf(th) / sinf(th);
+    const float zs = cot >= 0.0f ? 1.0f : -1.0f;
+    float x = 0.0f, y = 0.0f, z = 0.0f, ph = phi0;
+    int ic = 0, kd = 0;
+    bool alive = true;
+    const int64_t h0 = offsets[t], L = offsets[t + 1] - h0;
+    for (int64_t j = 0; j < L; ++j) {
+        const int64_t h = h0 + j;
+        float m[3] = {NAN, NAN, NAN};
+        int type = 0;
+        float val = 0.0f;
+        if (alive && (ic < 25 || kd < 25)) {
+            float sphi, cphi;
+            sincosf(ph, &sphi, &cphi);
+            float sc = INFINITY, sd = INFINITY;
+            HelixT<float> hc, hd;
+            if (ic < 25) {
+                const float R = 2.5f + (float)ic * (107.5f / 24.0f);
+                bool lok;
+                int it = 0;
+                float sn;
+                if (cylinder_reachable(x, y, cphi, sphi, w, R) &&
+                    newton_cylinder(x, y, cphi, sphi, w, R, newton_tol(1e-6f, R), 16,
+                                    line_path(x, y, cphi, sphi, R, &lok), sn, hc, it) &&
+                    sn > 0.0f && fabsf(w * sn) <= PI_F)
+                    sc = sn;
+            }
+            if (kd < 25 && cot != 0.0f) {
+                const float Z = zs * (30.0f + (float)kd * 10.0f);
+                const float sn = (Z - z) / cot;
+                if (sn > 0.0f && fabsf(w * sn) <= PI_F) {
+                    sd = sn;
+                    helix_at(x, y, cphi, sphi, w, sd, hd);
+                }
+            }
+            if (sc < sd) {
+                type = 0; val = 2.5f + (float)ic * (107.5f / 24.0f); ++ic;
+                x = hc.x; y = hc.y; z = z + sc * cot; ph = ph + 2.0f * hc.u;
+            } else if (sd < INFINITY) {
+                type = 1; val = zs * (30.0f + (float)kd * 10.0f); ++kd;
+                x = hd.x; y = hd.y; z = val; ph = ph + 2.0f * hd.u;
+            } else {
+                alive = false;
+            }
+            if (alive && (x * x + y * y > 110.0f * 110.0f * 1.0001f || fabsf(z) > 270.0f * 1.0001f)) alive = false;
+            if (alive) { m[0] = x; m[1] = y; m[2] = z; }
+        }
+        stype[h] = (uint8_t)type;
+        sval[h] = val;
+        for (int k = 0; k < 3; ++k) hpos[h * 3 + k] = m[k];
+        const float V[6] = {1e-4f, 0.0f, 1e-4f, 0.0f, 0.0f, type == 0 ? 1e-2f : 1e-4f};
+        for (int k = 0; k < 6; ++k) hcov[h * 6 + k] = V[k];
+    }
+}
+
+hipError_t launch_ragged_synth(int32_t n, int lmax, const int64_t* offsets, uint8_t* stype, float* sval,
+                               float* hpos, float* hcov, float* par, float* cov, int8_t* q, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rag_synth, dim3((n + 255) / 256), dim3(256), 0, s, n, lmax, offsets, stype, sval, hpos, hcov,
+                       par, cov, q);
+    return hipGetLastError();
 }
 
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s) {
@@ -440,9 +528,8 @@ hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& 
     const int64_t nwg = ((int64_t)a.n + RAG_TPB - 1) / RAG_TPB;
     if (nwg > 0) {
         hipLaunchKernelGGL(rag_hist, dim3((unsigned)nwg), dim3(tb), lds_keys, s, aa);
-        hipLaunchKernelGGL(rag_scan, dim3(1), dim3(1024), lds_keys, s, aa);
+        hipLaunchKernelGGL(rag_scan, dim3(1), dim3(1024), 0, s, aa);
         hipLaunchKernelGGL(rag_scatter, dim3((unsigned)nwg), dim3(tb), 2 * lds_keys, s, aa);
-        hipLaunchKernelGGL(rag_pack, dim3(a.nb), dim3(PACK_THREADS), 0, s, aa);
         void* args[] = {&aa, &pp};
         hipError_t e = hipLaunchKernel(v.fn, dim3(v.per_block ? a.nb : a.grid), dim3(RAG_W), args, 0, s);
         if (e != hipSuccess) return e;

@@ -293,11 +293,14 @@ __device__ __forceinline__ bool closed_form_cylinder(T x, T y, T cphi, T sphi, T
 // Newton iteration on f(s) = (r(s)^2 - R^2) / (2R) (= r - R near the root)
 // from s0 (the straight-line root or a proposal).  Stops when |f| <= tol; returns false
 // after max_iter helix evaluations without convergence.  h holds the last
-// evaluation.
+// evaluation, at s; *ds the Newton step that evaluation calls for, f / f',
+// which the caller applies to first order (finish_crossing): at grazing
+// incidence f' = cos(incidence) is small, and a residual |f| <= tol still
+// leaves the crossing tol / cos(incidence) away along the track.
 template <typename T>
 __device__ __forceinline__ bool newton_cylinder(T x, T y, T cphi, T sphi, T w, T R,
                                                 T tol, int max_iter, T s0, T& s, HelixT<T>& h,
-                                                int& iters, bool have_first = false) {
+                                                int& iters, bool have_first = false, T* ds = nullptr) {
     const T invR = rcp_(R);
     const T inv2R = T(0.5) * invR;
     s = s0;
@@ -305,11 +308,35 @@ __device__ __forceinline__ bool newton_cylinder(T x, T y, T cphi, T sphi, T w, T
         if (!(have_first && it == 0)) helix_at(x, y, cphi, sphi, w, s, h);
         T f = (fma_(h.x, h.x, h.y * h.y) - R * R) * inv2R;
         iters = it + 1;
-        if (fabs(f) <= tol) return true;
         T fp = (h.x * h.cp + h.y * h.sp) * invR;
-        s -= div_(f, fp);
+        T step = div_(f, fp);
+        if (fabs(f) <= tol) {
+            if (ds) *ds = step;
+            return true;
+        }
+        s -= step;
     }
     return false;
+}
+
+// Moves a crossing found by newton_cylinder by its last Newton step -ds, to
+// first order along the track: position along (cos phi', sin phi'), phi' by
+// omega times the step.  The second-order remainder, |ds|^2 / (2R), is far
+// below any tolerance for |ds| <= 0.1 cm; a larger step (a track tangent to
+// the surface, where the crossing itself is ill-defined) is not applied.
+// Returns the step applied.
+template <typename T>
+__device__ __forceinline__ T finish_crossing(T w, T ds, T& s, HelixT<T>& h) {
+    const T d = fabs(ds) <= T(0.1) ? ds : T(0);
+    s -= d;
+    h.x = fma_(-d, h.cp, h.x);
+    h.y = fma_(-d, h.sp, h.y);
+    const T dphi = -w * d;
+    h.u = fma_(T(0.5), dphi, h.u);
+    const T cp = h.cp, sp = h.sp;
+    h.cp = fma_(-sp, dphi, cp);
+    h.sp = fma_(cp, dphi, sp);
+    return d;
 }
 
 // -------------------------------------------------------- Jacobian blocks
@@ -331,10 +358,15 @@ struct JacT {
 // Cylinder: g = x'^2 + y'^2 - R^2, dg/ds = 2 D, D = x' cos phi' + y' sin phi'.
 // ds/dx = -x'/D, ds/dy = -y'/D, ds/dphi = -(x' y - x y')/D,
 // ds/dipt = -kq (x' dx'/domega + y' dy'/domega)/D, ds/dz = ds/dtheta = 0.
+// d: the step finish_crossing applied after the last helix evaluation (the
+// displacements x' - x = chord cos(phi_m), y' - y = chord sin(phi_m) move by
+// -d (cos phi', sin phi')).
 template <typename T>
 __device__ __forceinline__ void jacobian_cylinder(T x, T y, T w, T kq, T s, T cot,
-                                                  T sinth, const HelixT<T>& h, JacT<T>& J) {
+                                                  T sinth, const HelixT<T>& h, JacT<T>& J, T d = T(0)) {
     T hs2 = T(0.5) * s * s;
+    const T dxp = fma_(-d, h.cp, h.chord * h.cm);    // x' - x
+    const T dyp = fma_(-d, h.sp, h.chord * h.sm);    // y' - y
     T dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
     T dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
     T iD = rcp_(h.x * h.cp + h.y * h.sp);
@@ -347,14 +379,14 @@ __device__ __forceinline__ void jacobian_cylinder(T x, T y, T w, T kq, T s, T co
     J.a[0][1] = h.cp * dsy;
     J.a[0][2] = T(0.0);
     J.a[0][3] = fma_(h.cp, dsipt, kq * dxw);
-    J.a[0][4] = fma_(h.cp, dsphi, -h.chord * h.sm);
+    J.a[0][4] = fma_(h.cp, dsphi, -dyp);
     J.a[0][5] = T(0.0);
     // y' row
     J.a[1][0] = h.sp * dsx;
     J.a[1][1] = fma_(h.sp, dsy, T(1.0));
     J.a[1][2] = T(0.0);
     J.a[1][3] = fma_(h.sp, dsipt, kq * dyw);
-    J.a[1][4] = fma_(h.sp, dsphi, h.chord * h.cm);
+    J.a[1][4] = fma_(h.sp, dsphi, dxp);
     J.a[1][5] = T(0.0);
     // phi' row
     J.a[2][0] = w * dsx;
@@ -941,21 +973,23 @@ __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3
         s0 = line_path(x, y, cphi, sphi, R, &line_ok);
         if (!line_ok && !closed_form_cylinder(x, y, cphi, sphi, w, R, s0)) { o.flags |= ST_NO_CROSSING; return o; }
     }
-    bool conv = newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, s0, s, h, o.iters, have_first);
+    T ds = T(0);
+    bool conv = newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, s0, s, h, o.iters, have_first, &ds);
     o.iters += pre;
     if (!conv || !(s > -T(BACK_TOL)) || fabs(w * s) > pi_<T>()) {
         T sc;
         if (!closed_form_cylinder(x, y, cphi, sphi, w, R, sc)) { o.flags |= ST_NO_CROSSING; return o; }
         int it2 = 0;
-        conv = newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, sc, s, h, it2);
+        conv = newton_cylinder(x, y, cphi, sphi, w, R, tol, P.max_iter, sc, s, h, it2, false, &ds);
         o.iters += it2;
         if (!conv || !(s > -T(BACK_TOL)) || fabs(w * s) > pi_<T>()) { o.flags |= ST_NEWTON_FAIL; return o; }
     }
+    const T dapp = finish_crossing(w, ds, s, h);
     T sinth, costh;
     sincos_(st.p[5], &sinth, &costh);
     T cot = div_(costh, sinth);
     JacT<T> J;
-    jacobian_cylinder(x, y, w, kq, s, cot, sinth, h, J);
+    jacobian_cylinder(x, y, w, kq, s, cot, sinth, h, J, dapp);
     st.p[0] = h.x;
     st.p[1] = h.y;
     st.p[2] = fma_(s, cot, st.p[2]);

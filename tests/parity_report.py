@@ -1,0 +1,142 @@
+"""Full-size parity report: every track of the p2r, p2z and ragged benchmark
+workloads fitted on the GPU and by the FP64 oracle, compared element by
+element.  Prints, per workload, the largest error of every output, how many
+covariance elements pass under each branch of the rule in tests/parity.py,
+and the distribution of the final-crossing conditioning 1/cos(incidence)
+over the elements that need it.
+
+Needs a GPU and the built libraries:  python -m tests.parity_report [--dump DIR]
+(--dump writes the GPU and oracle outputs of the tracks that fail a check
+to DIR/parity_fail_<workload>.npz.)
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+
+def _gpu_p2r(p2r, ctx, d, W):
+    import torch
+    n = d["par"].shape[0]
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device="cuda")
+    hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device="cuda")
+    radii = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
+    out, chi2, st = ctx.p2r_propagate_update(n, radii, trk, hits, width=W)
+    torch.cuda.synchronize()
+    par, cov, _ = p2r.unpack_tracks(out, n)
+    return dict(par=par.cpu().numpy(), cov=cov.cpu().numpy(), chi2=chi2.cpu().numpy(),
+                status=st.cpu().numpy().view(np.uint32))
+
+
+def _gpu_p2z(p2r, ctx, d):
+    import torch
+    n = d["par"].shape[0]
+    trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64, device="cuda")
+    hits = p2r.pack_hits_p2z(d["hits"], d["hitcov"], device="cuda")
+    zs = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
+    out, chi2, st = ctx.p2z_propagate_update(n, zs, trk, hits)
+    torch.cuda.synchronize()
+    par, cov, _ = p2r.unpack_tracks(out, n)
+    return dict(par=par.cpu().numpy(), cov=cov.cpu().numpy(), chi2=chi2.cpu().numpy(),
+                status=st.cpu().numpy().view(np.uint32))
+
+
+def _gpu_ragged(p2r, ctx, d, cut):
+    import torch
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")  # noqa: E731
+    po, co, c2, st = ctx.fit_tracks_batched(
+        torch.as_tensor(d["offsets"], dtype=torch.int64, device="cuda"),
+        torch.as_tensor(d["surf_type"], dtype=torch.uint8, device="cuda"), f(d["surf_val"]), f(d["hits"]),
+        f(d["hitcov"]), f(d["par"]), f(d["cov"]), torch.as_tensor(d["q"], dtype=torch.int8, device="cuda"),
+        int(d["offsets"][-1]), 25, stream=torch.cuda.Stream(), chi2_cut=cut)
+    torch.cuda.synchronize()
+    return dict(par=po.cpu().numpy(), cov=co.cpu().numpy(), chi2=c2.cpu().numpy(),
+                status=st.cpu().numpy().view(np.uint32))
+
+
+def report(name, g, r, final_surface, dump=None):
+    from tests.parity import NORM_TOL, compare, covariance_breakdown, failures
+    f = failures(g, r, final_surface)
+    n = len(g["chi2"])
+    print(f"== {name}: {n} tracks, {len(f['excluded'])} excluded", flush=True)
+    bad = {k: f[k] for k in ("status", "par", "chi2", "cov")}
+    print("  tracks failing: " + ", ".join(f"{k} {len(v)}" for k, v in bad.items()))
+    for k in ("par", "chi2", "cov"):
+        rr = f[k + "_ratio"]
+        print(f"  {k}: largest error / tolerance {rr.max():.3f}; 99.99% {np.quantile(rr, 0.9999):.3f}; "
+              f"99.9% {np.quantile(rr, 0.999):.3f}")
+    if dump is not None:
+        idx = np.unique(np.concatenate([v for v in bad.values()] + [np.zeros(0, np.int64)])).astype(np.int64)
+        np.savez(dump, idx=idx, **{f"g_{k}": np.asarray(g[k])[idx] for k in ("par", "cov", "chi2", "status")},
+                 **{f"r_{k}": np.asarray(r[k])[idx] for k in ("par", "cov", "chi2", "status", "nused")})
+    if any(len(v) for v in bad.values()):
+        return None
+    rep = compare(g, r, ctx=name, final_surface=final_surface)
+    br = covariance_breakdown(g, r, final_surface)
+    print("  max rel error, parameters (x y z 1/pT phi theta):",
+          " ".join(f"{v:.2e}" for v in rep["max_rel_par"]))
+    print(f"  max rel error, chi2: {rep['max_rel_chi2']:.2e}")
+    print(f"  covariance, error / sqrt(C_ii C_jj): max {rep['cov_norm_err_max']:.2e}, "
+          f"99.9% {rep['cov_norm_err_p999']:.2e} (bound {NORM_TOL:g})")
+    print(f"  covariance elements: {rep['cov_rel_pass']} pass the relative bound, "
+          f"{rep['cov_norm_only']} only the normalised one, {rep['cov_kappa_only']} only with the "
+          f"conditioning factor; {rep['fp64_fallbacks']} tracks took the FP64 update")
+    print(f"  tracks ending on a cylinder with 1/cos(incidence) above 2, 5, 10, 20, 50: "
+          + ", ".join(str(c) for c in br["kappa_counts"]))
+    if br["needs_kappa"]:
+        print(f"  elements that need the factor: {br['needs_kappa']} in {br['tracks_kappa']} tracks; "
+              f"per packed index {br['per_index']}")
+        print(f"  required factor / track's 1/cos(incidence): max {br['ratio_max']:.3f}; "
+              f"their 1/cos(incidence): min {br['kappa_min']:.1f}, max {br['kappa_max']:.1f}")
+    return rep
+
+
+def _dump(name):
+    """Where the failing tracks' outputs go (a --dump DIR argument), or None."""
+    if "--dump" not in sys.argv:
+        return None
+    import os
+    d = sys.argv[sys.argv.index("--dump") + 1]
+    os.makedirs(d, exist_ok=True)
+    return os.path.join(d, f"parity_fail_{name}.npz")
+
+
+def main():
+    import torch  # noqa: F401
+
+    import oracle
+    import paper_2401_14221_amd as p2r
+    from synth import events as ev
+    from tests.parity import final_surface_of
+
+    ctx = p2r.Context(0)
+    t = time.time()
+    d = ev.make_barrel_event(ev.P2R_THROUGHPUT)
+    W = 256
+    g = _gpu_p2r(p2r, ctx, d, W)
+    r = oracle.fit_event(d, "barrel", nthreads=16)
+    report(f"p2r {ev.P2R_THROUGHPUT.name} (W={W})", g, r, "cylinder", dump=_dump("p2r"))
+    print(f"  ({time.time() - t:.0f} s)", flush=True)
+    del d, g, r
+    t = time.time()
+    d = ev.make_disk_event(ev.P2Z_THROUGHPUT)
+    g = _gpu_p2z(p2r, ctx, d)
+    r = oracle.fit_event(d, "disk", nthreads=16)
+    report(f"p2z {ev.P2Z_THROUGHPUT.name}", g, r, "plane", dump=_dump("p2z"))
+    print(f"  ({time.time() - t:.0f} s)", flush=True)
+    del d, g, r
+    t = time.time()
+    d = ev.make_ragged_event(ev.RAGGED)
+    cut = 30.0
+    g = _gpu_ragged(p2r, ctx, d, cut)
+    r = oracle.fit_ragged(d, chi2_cut=cut, nthreads=16)
+    fs = final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"])
+    report(f"ragged {ev.RAGGED.name} (chi2 cut {cut:g})", g, r, fs, dump=_dump("ragged"))
+    print(f"  ({time.time() - t:.0f} s)", flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    sys.exit(main())

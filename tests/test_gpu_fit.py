@@ -293,3 +293,43 @@ def test_every_plain_variant_matches_oracle():
             else:
                 compare(run_p2z(c, dz), rz, ctx=name, final_surface="plane")
             c.close()
+
+
+def test_zero_layers_pass_tracks_through(ctx):
+    """n_layers = 0 with no hit or layer buffer at all: every track comes back
+    unchanged, with chi2 0 and no surface used (nothing is read from the
+    missing buffers)."""
+    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=300)
+    empty = torch.empty(0, dtype=torch.float32, device="cuda")
+    for which, W in ((0, 64), (0, 256), (1, 64)):
+        trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device="cuda")
+        fit = ctx.p2r_propagate_update if which == 0 else ctx.p2z_propagate_update
+        kw = {"width": W} if which == 0 else {}
+        out, chi2, st = fit(300, empty, trk, None, **kw)
+        torch.cuda.synchronize()
+        par, cov, q = p2r.unpack_tracks(out, 300)
+        par0, cov0, q0 = p2r.unpack_tracks(trk, 300)
+        assert torch.equal(par, par0) and torch.equal(cov, cov0) and torch.equal(q, q0)
+        assert torch.all(chi2 == 0)
+        assert np.all(st.cpu().numpy().view(np.uint32) == p2r.ST_DONE)
+
+
+def test_helix_evaluation_count_with_a_partial_wave(ctx):
+    """The evaluation counter of a launch whose last wave is partly past n
+    equals the count derived from launches made of whole waves only: the
+    first n tracks plus copies of the last one up to a whole number of
+    blocks, minus the copies' share measured on a launch of copies alone."""
+    n, full = 1000, 1024
+    d = ev.make_barrel_event(ev.P2R_THROUGHPUT.with_(seed=71), n_tracks=n)
+
+    def count(dd, m):
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        run_p2r(ctx, dd, 64, helix_evals=cnt.data_ptr())
+        return int(cnt.item())
+
+    pad = np.concatenate([np.arange(n), np.full(full - n, n - 1)])
+    e_tail = count(d, n)
+    e_pad = count(_sub(d, pad), full)
+    e_copies = count(_sub(d, np.full(full, n - 1)), full)
+    assert e_copies % full == 0
+    assert e_tail == e_pad - (full - n) * (e_copies // full)

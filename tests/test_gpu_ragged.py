@@ -59,11 +59,20 @@ def test_ragged_parity_small(ctx):
     assert np.all(((g["status"] >> 8) & 0xFF) <= L)
 
 
-@pytest.mark.parametrize("variant", ["rag_fit_grid", "rag_fit_e0", "rag_fit_e4"])
+def _ragged_variants():
+    import paper_2401_14221_amd as m
+    try:
+        return m.variant_names(2)
+    except Exception:
+        return ["rag_fit_c4"]
+
+
+@pytest.mark.parametrize("variant", _ragged_variants())
 def test_ragged_fit_variants(variant):
-    """Every plain fit kernel (one workgroup per block, and the persistent
-    work queue at both occupancy targets) against the oracle, in a context of
-    its own so that the choice does not leak into the other tests."""
+    """Every plain fit kernel (staged chunks of 2, 4 or 8 surfaces, with and
+    without prefetch, both occupancy targets, the per-block grid and the
+    persistent work queue) against the oracle, in a context of its own so
+    that the choice does not leak into the other tests."""
     assert variant in p2r.variant_names(2)
     c = p2r.Context(0)
     try:
@@ -163,3 +172,83 @@ def test_ragged_full_size_sampled(ctx):
     rep = compare({k: v[idx] for k, v in g.items()}, r, ctx="ragged full",
                   final_surface=final_surface_of(r["par"], sub_off, sub["surf_type"], sub["surf_val"]))
     print("ragged full sampled", rep, flush=True)
+
+
+def test_ragged_autotune_picks_and_caches(tmp_path):
+    """The ragged autotuner times the compiled variants on synthetic mixed
+    tracks, keeps one, writes it to the cache (keyed by this build's source
+    hash) and serves it from there; the tuned choice matches the oracle."""
+    cache = tmp_path / "tune.json"
+    c = p2r.Context(0, tune_cache=str(cache))
+    c2 = None
+    try:
+        c.autotune(2, 30000, 25)
+        name = c.variant_name(2)
+        assert name in p2r.variant_names(2)
+        txt = cache.read_text()
+        assert "|2|30000|25|" in txt and name in txt
+        assert p2r.library().p2r_version().decode() in txt
+        c2 = p2r.Context(0, tune_cache=str(cache))    # reads the cache that c wrote
+        c2.autotune(2, 30000, 25)
+        assert c2.variant_name(2) == name
+        d = ev.make_ragged_event(ev.RAGGED.with_(seed=97), n_tracks=6000)
+        r = oracle.fit_ragged(d, chi2_cut=CUT)
+        g = run(c2, upload(d), int(d["offsets"][-1]), stream=torch.cuda.Stream())
+        compare(g, r, ctx=f"tuned {name}",
+                final_surface=final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"]))
+    finally:
+        c.close()
+        if c2 is not None:
+            c2.close()
+
+
+def test_ragged_workspace_must_be_reserved():
+    """Without p2r_ctx_reserve the C call refuses (P2R_ENOSPACE) and launches nothing."""
+    import ctypes as C
+    from paper_2401_14221_amd import _lib
+    c = p2r.Context(0)
+    try:
+        d = ev.make_ragged_event(ev.RAGGED.with_(seed=31), n_tracks=100)
+        u = upload(d)
+        n = 100
+        outs = [torch.zeros((n, 6), device="cuda"), torch.zeros((n, 21), device="cuda"),
+                torch.zeros(n, device="cuda"), torch.zeros(n, dtype=torch.int32, device="cuda")]
+        o = _lib.default_opts(use_graph=0)
+        ptr = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+        args = [ptr(u[k]) for k in ("offsets", "surf_type", "surf_val", "hit_pos", "hit_cov", "par_in", "cov_in", "q")]
+        rc = _lib.library().fit_tracks_batched(c._h, C.byref(o), n, int(d["offsets"][-1]), 25, *args,
+                                               *[ptr(t) for t in outs], None)
+        assert rc == p2r.P2R_ENOSPACE and b"p2r_ctx_reserve" in _lib.library().p2r_last_error()
+        torch.cuda.synchronize()
+        assert torch.all(outs[3] == 0)
+        c.reserve(100, 25)
+        rc = _lib.library().fit_tracks_batched(c._h, C.byref(o), n, int(d["offsets"][-1]), 25, *args,
+                                               *[ptr(t) for t in outs], None)
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert np.all((outs[3].cpu().numpy().view(np.uint32) & p2r.ST_DONE) != 0)
+    finally:
+        c.close()
+
+
+def test_no_device_allocation_after_reserve():
+    """After the sizing call, fits (eager, graph capture and replays, a
+    smaller problem) make no device allocation."""
+    c = p2r.Context(0)
+    try:
+        d = ev.make_ragged_event(ev.RAGGED.with_(seed=33), n_tracks=4000)
+        u = upload(d)
+        H = int(d["offsets"][-1])
+        c.reserve(4000, 25)
+        s = torch.cuda.Stream()
+        outs = (torch.empty((4000, 6), device="cuda"), torch.empty((4000, 21), device="cuda"),
+                torch.empty(4000, device="cuda"), torch.empty(4000, dtype=torch.int32, device="cuda"))
+        torch.cuda.synchronize()
+        n0 = p2r.device_allocations()
+        for use_graph in (0, 1, 1, 1):
+            run(c, u, H, out=outs, stream=s, use_graph=use_graph)
+        e = ev.make_ragged_event(ev.RAGGED.with_(seed=34), n_tracks=1500)
+        run(c, upload(e), int(e["offsets"][-1]), stream=s)
+        assert p2r.device_allocations() == n0
+    finally:
+        c.close()
