@@ -74,6 +74,10 @@ extern "C" {
 /* Largest n_hits of one fit_tracks_batched call (the ragged fit addresses
  * its CSR arrays with 32-bit byte offsets: 24 * n_hits < 2^32). */
 #define P2R_MAX_HITS 178956970LL
+/* Limits of fit_tracks_batched_noalloc: tracks per call, and the bytes of
+ * device memory its scratch array holds on every GPU the library runs on. */
+#define P2R_NOALLOC_MAX_TRACKS 1048576
+#define P2R_NOALLOC_SCRATCH_BYTES 16794368ULL
 
 typedef struct p2r_ctx p2r_ctx; /* opaque: device, tuned variants, workspace, graphs */
 
@@ -187,7 +191,7 @@ int p2z_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_trac
  *   track's count (<= 255; a track with more, or a negative count, is
  *   BAD_INPUT).
  *   offsets [n_tracks+1] (int64, offsets[0] = 0), surf_type [n_hits] (uint8),
- *   surf_val [n_hits], hit_pos [n_hits][3], hit_cov [n_hits][6] (packed),
+ *   surf_val [n_hits], hit_pos [n_hits][3], hit_cov [n_hits][6] (packed; 8-byte aligned),
  *   par_in [n][6], cov_in [n][21], q [n] (int8 +-1); outputs par_out [n][6],
  *   cov_out [n][21], chi2_out [n], status [n].  A surf_type other than 0/1
  *   skips that surface and sets BAD_INPUT.
@@ -207,6 +211,24 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
                        const float* surf_val, const float* hit_pos, const float* hit_cov,
                        const float* par_in, const float* cov_in, const int8_t* q, float* par_out,
                        float* cov_out, float* chi2_out, uint32_t* status, void* stream);
+
+/* fit_tracks_batched for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, layouts, options and results as
+ * fit_tracks_batched, but the sort arrays live in a scratch array that the
+ * library holds in static device memory, P2R_NOALLOC_SCRATCH_BYTES on every
+ * GPU it runs on (until the process ends), instead of the context's reserved
+ * workspace.  Needs no p2r_ctx_reserve; allocates nothing and captures no
+ * graph (the kernels are launched directly on `stream`, so the call itself may
+ * be captured by the caller).  At most P2R_NOALLOC_MAX_TRACKS tracks
+ * (P2R_ENOSPACE beyond, nothing launched).  Every call on one GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (other streams, other
+ * contexts, other threads) race and give wrong results; serialise them. */
+int fit_tracks_batched_noalloc(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits,
+                               int32_t max_surfaces, const int64_t* offsets, const uint8_t* surf_type,
+                               const float* surf_val, const float* hit_pos, const float* hit_cov,
+                               const float* par_in, const float* cov_in, const int8_t* q, float* par_out,
+                               float* cov_out, float* chi2_out, uint32_t* status, void* stream);
 
 /* Autotune `which` (0 p2r, 1 p2z, 2 ragged) on synthetic tracks of this
  * shape: times every compiled plain variant with HIP events, keeps the

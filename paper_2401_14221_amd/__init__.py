@@ -7,7 +7,7 @@ device memory and streams.  The library must have been built
 or calling it without a GPU, raises instead of falling back to anything.
 """
 from ._lib import (  # noqa: F401
-    P2R_OK, P2R_EINVAL, P2R_ELAYOUT, P2R_EHIP, P2R_ENOTUNED, P2R_ENOSPACE,
+    P2R_OK, P2R_EINVAL, P2R_ELAYOUT, P2R_EHIP, P2R_ENOTUNED, P2R_ENOSPACE, P2R_MAX_HITS, P2R_NOALLOC_MAX_TRACKS,
     ST_NO_CROSSING, ST_NEWTON_FAIL, ST_FP64_FALLBACK, ST_S_NOT_PD, ST_BAD_INPUT,
     ST_ML_REJECTED, ST_HIT_MISSING, ST_CHI2_CUT, ST_DONE, P2RError, Opts, Context, Mlp,
     library, library_path, exported_symbols, variant_names, device_allocations,

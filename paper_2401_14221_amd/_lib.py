@@ -23,6 +23,18 @@ ST_CHI2_CUT = 1 << 7
 ST_DONE = 1 << 31
 
 
+def _header_define(name: str) -> int:
+    """Integer value of a #define in include/p2r.h (one source for the limits)."""
+    m = re.search(rf"^#define {name} \(?(-?\d+)", open(_HEADER).read(), flags=re.M)
+    if not m:
+        raise RuntimeError(f"{name} is not defined in {_HEADER}")
+    return int(m.group(1))
+
+
+P2R_MAX_HITS = _header_define("P2R_MAX_HITS")
+P2R_NOALLOC_MAX_TRACKS = _header_define("P2R_NOALLOC_MAX_TRACKS")
+
+
 class P2RError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libp2r error {code}: {msg}")
@@ -71,6 +83,7 @@ def library():
         L.p2r_variant_at.argtypes = [C.c_int, C.c_int]
         L.p2r_variant_at.restype = C.c_char_p
         L.fit_tracks_batched.argtypes = [vp, C.POINTER(Opts), i32, i64, i32] + [vp] * 13
+        L.fit_tracks_batched_noalloc.argtypes = [vp, C.POINTER(Opts), i32, i64, i32] + [vp] * 13
         L.p2r_ctx_reserve.argtypes = [vp, i32, i32]
         L.p2r_device_allocations.restype = C.c_ulonglong
         L.p2r_mlp_create.argtypes = [vp, C.POINTER(vp)]
@@ -245,6 +258,20 @@ class Context:
                                             _ptr(cov_in), _ptr(q), _ptr(par_out), _ptr(cov_out), _ptr(chi2),
                                             _ptr(status), _stream(stream)))
         return par_out, cov_out, chi2, status
+
+
+    def fit_tracks_batched_noalloc(self, offsets, surf_type, surf_val, hit_pos, hit_cov, par_in, cov_in, q,
+                                   n_hits, max_surfaces, out, opts=None, stream=None, **kw):
+        """The ragged fit without any allocation (library-held scratch, no graph):
+        `out` = (par_out, cov_out, chi2, status) must be given; returns it."""
+        opts = opts or default_opts(**kw)
+        par_out, cov_out, chi2, status = out
+        _check(library().fit_tracks_batched_noalloc(self._h, C.byref(opts), par_in.shape[0], int(n_hits),
+                                                    int(max_surfaces), _ptr(offsets), _ptr(surf_type),
+                                                    _ptr(surf_val), _ptr(hit_pos), _ptr(hit_cov), _ptr(par_in),
+                                                    _ptr(cov_in), _ptr(q), _ptr(par_out), _ptr(cov_out), _ptr(chi2),
+                                                    _ptr(status), _stream(stream)))
+        return out
 
 
 class Mlp:

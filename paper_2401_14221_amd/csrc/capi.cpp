@@ -11,6 +11,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -64,6 +65,55 @@ struct DeviceGuard {
     }
 };
 
+// ------------------------------------------- scratch of the no-alloc fit
+// fit_tracks_batched_noalloc works in this array instead of a context's
+// workspace: the sort-key histogram and bucket starts (for up to 255
+// surfaces per track), the work counter, and the sort arrays (perm, keys,
+// run) for up to P2R_NOALLOC_MAX_TRACKS tracks, each at a 256-byte boundary.
+// Every GPU the library runs on holds one copy until the process ends.  In
+// host code the array's name is not a device address: the address of this
+// GPU's copy comes from hipGetSymbolAddress, taken once per device when a
+// context is created on it (scratch_setup), and only that address is used.
+constexpr size_t NA_KEYS = 256 * p2r::RAG_ETA_BINS + 1;       // sort keys for max_surfaces = 255
+constexpr size_t na_round(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t NA_HIST = 0;
+constexpr size_t NA_BASE = NA_HIST + na_round(4 * NA_KEYS);
+constexpr size_t NA_WORK = NA_BASE + na_round(4 * NA_KEYS);
+constexpr size_t NA_PERM = NA_WORK + 256;
+constexpr size_t NA_KEYS_OFF = NA_PERM + na_round(4 * (size_t)P2R_NOALLOC_MAX_TRACKS);
+constexpr size_t NA_RUN = NA_KEYS_OFF + na_round(4 * (size_t)P2R_NOALLOC_MAX_TRACKS);
+constexpr size_t NA_BYTES = NA_RUN + na_round(8 * (size_t)P2R_NOALLOC_MAX_TRACKS);
+static_assert(NA_BYTES == P2R_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[NA_MAX_DEVICES] = {};   // this device's copy of `scratch`, or null before setup
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+
+// Takes this device's address of `scratch` (the device must be current).
+int scratch_setup(int device) {
+    if (device < 0 || device >= NA_MAX_DEVICES) return fail(P2R_EINVAL, "device %d beyond %d", device, NA_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return P2R_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (scratch)");
+    if (!ptr) return fail(P2R_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[device] = static_cast<char*>(ptr);
+    return P2R_OK;
+}
+
+char* scratch_of(int device) {
+    if (device < 0 || device >= NA_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 // Arguments a captured ragged graph was recorded with; a call with other
@@ -95,7 +145,7 @@ struct p2r_ctx {
     int32_t* rag_keys = nullptr;
     int64_t* rag_run = nullptr;
     int32_t rag_n_cap = 0, rag_nkeys_cap = 0, rag_lmax_cap = -1;
-    std::map<const void*, int> rag_blocks_per_cu;   // resident workgroups per CU of each persistent fit
+    std::vector<int> rag_blocks_per_cu;   // resident workgroups per CU of each ragged fit variant (by index)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     RaggedKey key;
@@ -282,6 +332,21 @@ int p2r_ctx_create(p2r_ctx** out, int device, const char* tune_cache_path) {
     c->cu_count = prop.multiProcessorCount;
     if (tune_cache_path) c->cache_path = tune_cache_path;
     load_cache(c.get());
+    {
+        DeviceGuard g(device);
+        if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+        const auto& vs = p2r::variants();
+        c->rag_blocks_per_cu.assign(vs.size(), 1);
+        for (size_t i = 0; i < vs.size(); ++i) {
+            if (vs[i].which != 2) continue;
+            int nb = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, vs[i].fn, p2r::RAG_W, 0);
+            if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+            c->rag_blocks_per_cu[i] = nb > 0 ? nb : 1;
+        }
+        int rc = scratch_setup(device);
+        if (rc) return rc;
+    }
     *out = c.release();
     g_err.clear();
     return P2R_OK;
@@ -523,13 +588,7 @@ static int ragged_launch_args(p2r_ctx* ctx, const p2r::Variant& v, int32_t n_tra
                               const float* surf_val, const float* hit_pos, const float* hit_cov,
                               const float* par_in, const float* cov_in, const int8_t* q, float* par_out,
                               float* cov_out, float* chi2_out, uint32_t* status, p2r::RaggedLaunch& a) {
-    int& bpc = ctx->rag_blocks_per_cu[v.fn];
-    if (bpc == 0) {
-        int nb = 0;
-        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v.fn, p2r::RAG_W, 0);
-        if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-        bpc = nb > 0 ? nb : 1;
-    }
+    const int bpc = ctx->rag_blocks_per_cu[&v - p2r::variants().data()];
     a = p2r::RaggedLaunch{};
     a.n = n_tracks;
     a.lmax = max_surfaces;
@@ -609,11 +668,14 @@ int p2r_ctx_reserve(p2r_ctx* ctx, int32_t max_tracks, int32_t max_surfaces) {
 
 unsigned long long p2r_device_allocations(void) { return g_allocs.load(std::memory_order_relaxed); }
 
-int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits, int32_t max_surfaces,
-                       const int64_t* offsets, const uint8_t* surf_type, const float* surf_val,
-                       const float* hit_pos, const float* hit_cov, const float* par_in, const float* cov_in,
-                       const int8_t* q, float* par_out, float* cov_out, float* chi2_out, uint32_t* status,
-                       void* stream) {
+// Argument checks shared by the ragged entry points (nothing launched on
+// failure); *v gets the variant the context uses.  Returns 1 (no error,
+// nothing to do) for an empty problem.
+static int ragged_check(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits, int32_t max_surfaces,
+                        const int64_t* offsets, const uint8_t* surf_type, const float* surf_val,
+                        const float* hit_pos, const float* hit_cov, const float* par_in, const float* cov_in,
+                        const int8_t* q, float* par_out, float* cov_out, float* chi2_out, uint32_t* status,
+                        const p2r::Variant** v) {
     if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
     int rc = check_opts(opts);
     if (rc) return rc;
@@ -623,25 +685,33 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     if (max_surfaces < 0 || max_surfaces > 255) return fail(P2R_EINVAL, "max_surfaces must be in [0, 255]");
     if (n_hits > (int64_t)n_tracks * max_surfaces)
         return fail(P2R_EINVAL, "n_hits %lld exceeds n_tracks * max_surfaces", (long long)n_hits);
-    if (n_tracks == 0) return P2R_OK;
-    if (!offsets || !par_in || !cov_in || !q || !par_out || !cov_out || !chi2_out || !status ||
-        (n_hits > 0 && (!surf_type || !surf_val || !hit_pos || !hit_cov)))
-        return fail(P2R_EINVAL, "NULL buffer");
-    const void* a8[] = {offsets};
-    const void* a4[] = {surf_val, hit_pos, hit_cov, par_in, cov_in, par_out, cov_out, chi2_out, status};
-    for (const void* p : a8)
-        if (!aligned(p, 8)) return fail(P2R_ELAYOUT, "offsets not 8-byte aligned");
-    for (const void* p : a4)
-        if (p && !aligned(p, 4)) return fail(P2R_ELAYOUT, "buffer not 4-byte aligned");
-    const p2r::Variant* v = nullptr;
-    rc = variant_for(ctx, 2, 0, &v, false, opts->fp64 != 0, opts->update_2d != 0);
-    if (rc) return rc;
-    DeviceGuard g(ctx->device);
-    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     // the fit addresses the CSR arrays with 32-bit byte offsets (hit_cov, 24 B per surface, the largest)
     if (n_hits > P2R_MAX_HITS)
         return fail(P2R_EINVAL, "n_hits %lld too large for one call (at most %lld)", (long long)n_hits,
                     (long long)P2R_MAX_HITS);
+    if (n_tracks == 0) return 1;
+    if (!offsets || !par_in || !cov_in || !q || !par_out || !cov_out || !chi2_out || !status ||
+        (n_hits > 0 && (!surf_type || !surf_val || !hit_pos || !hit_cov)))
+        return fail(P2R_EINVAL, "NULL buffer");
+    const void* a4[] = {surf_val, hit_pos, hit_cov, par_in, cov_in, par_out, cov_out, chi2_out, status};
+    if (!aligned(offsets, 8)) return fail(P2R_ELAYOUT, "offsets not 8-byte aligned");
+    if (hit_cov && !aligned(hit_cov, 8)) return fail(P2R_ELAYOUT, "hit_cov not 8-byte aligned");
+    for (const void* p : a4)
+        if (p && !aligned(p, 4)) return fail(P2R_ELAYOUT, "buffer not 4-byte aligned");
+    return variant_for(ctx, 2, 0, v, false, opts->fp64 != 0, opts->update_2d != 0);
+}
+
+int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits, int32_t max_surfaces,
+                       const int64_t* offsets, const uint8_t* surf_type, const float* surf_val,
+                       const float* hit_pos, const float* hit_cov, const float* par_in, const float* cov_in,
+                       const int8_t* q, float* par_out, float* cov_out, float* chi2_out, uint32_t* status,
+                       void* stream) {
+    const p2r::Variant* v = nullptr;
+    int rc = ragged_check(ctx, opts, n_tracks, n_hits, max_surfaces, offsets, surf_type, surf_val, hit_pos, hit_cov,
+                          par_in, cov_in, q, par_out, cov_out, chi2_out, status, &v);
+    if (rc) return rc > 0 ? P2R_OK : rc;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     // the workspace comes from p2r_ctx_reserve: nothing is allocated here
     const int nkeys = p2r::ragged_nkeys(max_surfaces);
     if (n_tracks > ctx->rag_n_cap || nkeys > ctx->rag_nkeys_cap || !ctx->rag_work)
@@ -693,6 +763,38 @@ int fit_tracks_batched(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int
     }
     if ((e = hipGraphLaunch(ctx->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return P2R_OK;
+}
+
+int fit_tracks_batched_noalloc(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int64_t n_hits,
+                               int32_t max_surfaces, const int64_t* offsets, const uint8_t* surf_type,
+                               const float* surf_val, const float* hit_pos, const float* hit_cov,
+                               const float* par_in, const float* cov_in, const int8_t* q, float* par_out,
+                               float* cov_out, float* chi2_out, uint32_t* status, void* stream) {
+    const p2r::Variant* v = nullptr;
+    int rc = ragged_check(ctx, opts, n_tracks, n_hits, max_surfaces, offsets, surf_type, surf_val, hit_pos, hit_cov,
+                          par_in, cov_in, q, par_out, cov_out, chi2_out, status, &v);
+    if (rc) return rc > 0 ? P2R_OK : rc;
+    if (n_tracks > P2R_NOALLOC_MAX_TRACKS)
+        return fail(P2R_ENOSPACE, "fit_tracks_batched_noalloc takes at most %d tracks (got %d)",
+                    (int)P2R_NOALLOC_MAX_TRACKS, n_tracks);
+    char* base = scratch_of(ctx->device);
+    if (!base) return fail(P2R_EHIP, "no scratch address for device %d", ctx->device);
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    p2r::RaggedLaunch a{};
+    if ((rc = ragged_launch_args(ctx, *v, n_tracks, n_hits, max_surfaces, offsets, surf_type, surf_val, hit_pos,
+                                 hit_cov, par_in, cov_in, q, par_out, cov_out, chi2_out, status, a)))
+        return rc;
+    // the sort arrays in this GPU's scratch instead of the context's workspace;
+    // rag_reset (a kernel) clears the histogram and the work counter each call
+    a.hist = reinterpret_cast<int32_t*>(base + NA_HIST);
+    a.base = reinterpret_cast<int32_t*>(base + NA_BASE);
+    a.work = reinterpret_cast<int32_t*>(base + NA_WORK);
+    a.perm = reinterpret_cast<int32_t*>(base + NA_PERM);
+    a.keys = reinterpret_cast<int32_t*>(base + NA_KEYS_OFF);
+    a.run = reinterpret_cast<int64_t*>(base + NA_RUN);
+    const hipError_t e = p2r::launch_ragged(*v, a, params_of(opts), (hipStream_t)stream);
+    return e == hipSuccess ? P2R_OK : hip_fail(e, "ragged launch");
 }
 
 // ------------------------------------------------------------------- MLP
