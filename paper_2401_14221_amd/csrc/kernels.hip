@@ -70,11 +70,11 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
     if (bad) flags = ST_BAD_INPUT;
     if (!bad || LEARNED) {
         const float* hb = a.hits + (size_t)b * ((size_t)a.L * 9 * W) + l;
-        float hm[9] = {};
-        if (a.L > 0) {                    // with no layers there may be no hit buffer at all
+        // with no layers the hit stream is the track records (launch_fit), so
+        // this first prefetch stays inside a buffer; its values are unused
+        float hm[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
-        }
+        for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
 #pragma unroll UNROLL
         for (int ly = 0; ly < a.L; ++ly) {
             const T m[3] = {hm[0], hm[1], hm[2]};
@@ -112,6 +112,7 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
     }
     count_evals(a.evals, active ? evals : 0);
     if (!active) return;
+    finalise(st);
     store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
     a.chi2[gid] = (float)chi2;
     a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
@@ -137,11 +138,9 @@ __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
         const T zsign = (float)st.p[5] < HALF_PI_F ? T(1) : T(-1);
         const size_t lstride = (size_t)nb * (9 * W);
         const float* hb = a.hits + (size_t)b * (9 * W) + l;
-        float hm[9] = {};
-        if (a.L > 0) {                    // with no layers there may be no hit buffer at all
+        float hm[9];                      // (no layers: see p2r_body)
 #pragma unroll
-            for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
-        }
+        for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
 #pragma unroll UNROLL
         for (int ly = 0; ly < a.L; ++ly) {
             const T m[3] = {hm[0], hm[1], hm[2]};
@@ -157,6 +156,7 @@ __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
             if (o.updated) { ++nused; chi2 += c2; }
         }
     }
+    finalise(st);
     store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
     a.chi2[gid] = (float)chi2;
     a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
@@ -277,6 +277,14 @@ hipError_t launch_fit(const Variant& v, const FitLaunch& a, const Params& P, hip
     const int blocks = (a.n + threads - 1) / threads;
     if (blocks == 0) return hipSuccess;
     FitLaunch aa = a;
+    // The kernels prefetch the first layer's hit before their layer loop.
+    // With no layers there may be no hit buffer: the prefetch then reads the
+    // track records instead, and stays inside them -- p2r reads floats
+    // l + k W (k < 9, l < W) and p2z reads 9 W b + k W + l of a record
+    // buffer of 28 W floats per block -- and its values are never used.
+    // (Guarding the prefetch with a branch on L instead made the learned
+    // 256-wide kernel return wrong results with this compiler.)
+    if (aa.L == 0) aa.hits = aa.trk_in;
     Params pp = P;
     void* args[] = {&aa, &pp};
     return hipLaunchKernel(v.fn, dim3(blocks), dim3(threads), args, 0, s);

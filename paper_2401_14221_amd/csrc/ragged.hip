@@ -375,6 +375,7 @@ __device__ __forceinline__ void fit_block(const RaggedLaunch& a, const Params& P
         if (!PREFETCH && k1 < rows) hit_load<C>(a, S.run, lane, k1, RH);
     }
     if (!live) return;
+    finalise(st);
 #pragma unroll
     for (int f = 0; f < 6; ++f) a.par_out[(size_t)t * 6 + f] = (float)st.p[f];
 #pragma unroll

@@ -121,13 +121,93 @@ struct Params {
     int32_t start_mode;   // cylinder start: 0 straight line (plain), 1 closed form
 };
 
+// lo: the low parts of the compensated components of an FP32 state (below).
 template <typename T>
 struct StateT {
     T p[6];
     T c[21];
     T q;
+    T lo[6] = {};
 };
 using State = StateT<float>;
+
+// ------------------------------------------------------ compensated state
+// An FP32 fit that rounds its state to FP32 after every propagation and
+// update loses, at r ~ 100 cm, 0.04 um of position per rounding, and for
+// theta near pi (ulp 2.4e-7 rad) the crossing of the next plane moves by
+// (Z - z) dtheta / cos^2(theta): over 20 layers enough to move the chi2 sum
+// of 100 um hits by 1e-3 of itself.  So the positions and angles (x, y, z,
+// phi, theta) are carried as unevaluated sums p[i] + lo[i] of two floats:
+// every increment is added with Dekker's Fast2Sum, whose rounding error goes
+// to lo[i]; residuals subtract lo[i]; the sines and cosines of phi and theta
+// are corrected to first order in lo[i]; and each step ends by renormalising
+// so that p[i] is the float nearest to the sum.  Fast2Sum is exact when
+// |p[i]| >= |increment|; otherwise (a position near 0 moved by a larger step)
+// it can lose up to half an ulp of the increment, no more than plain
+// rounding would, at a point where that ulp is small.  1/pT and the
+// covariance stay plain FP32.  The FP64 fit carries no low parts.
+constexpr int N_COMP = 5;
+__device__ __forceinline__ constexpr int comp_index(int k) { return k < 3 ? k : k + 1; }   // x y z phi theta
+
+template <typename T>
+__device__ __forceinline__ void add_to(StateT<T>& st, int i, T d) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+        const T a = st.p[i];
+        const T s = a + d;
+        st.lo[i] += d - (s - a);
+        st.p[i] = s;
+    } else {
+        st.p[i] += d;
+    }
+}
+
+// p[i] <- the float nearest to p[i] + lo[i], lo[i] <- the remainder (z is
+// left as it is: it enters only residuals and path lengths, which use the
+// sum, and a plane resets it)
+template <typename T>
+__device__ __forceinline__ void renormalise(StateT<T>& st) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+        constexpr int idx[4] = {0, 1, 4, 5};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = idx[k];
+            const T s = st.p[i] + st.lo[i];
+            st.lo[i] = st.lo[i] - (s - st.p[i]);
+            st.p[i] = s;
+        }
+    }
+}
+
+// the parameters as FP32 values: each the float nearest to p[i] + lo[i]
+template <typename T>
+__device__ __forceinline__ void finalise(StateT<T>& st) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+#pragma unroll
+        for (int k = 0; k < N_COMP; ++k) {
+            const int i = comp_index(k);
+            st.p[i] += st.lo[i];
+            st.lo[i] = T(0);
+        }
+    }
+}
+
+// m - (p[i] + lo[i])
+template <typename T>
+__device__ __forceinline__ T residual_of(const StateT<T>& st, int i, T m) {
+    if constexpr (sizeof(T) == sizeof(float)) return (m - st.p[i]) - st.lo[i];
+    else return m - st.p[i];
+}
+
+// sin and cos of p[i] + lo[i] from those of p[i], to first order in lo[i]
+template <typename T>
+__device__ __forceinline__ void sincos_comp(const StateT<T>& st, int i, T* sn, T* cs) {
+    sincos_(st.p[i], sn, cs);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        const T s0 = *sn, c0 = *cs, d = st.lo[i];
+        *sn = fma_(c0, d, s0);
+        *cs = fma_(-s0, d, c0);
+    }
+}
 
 // ---------------------------------------------------------------- helix
 // Point of the helix at transverse path s, in the half-angle form
@@ -358,15 +438,13 @@ struct JacT {
 // Cylinder: g = x'^2 + y'^2 - R^2, dg/ds = 2 D, D = x' cos phi' + y' sin phi'.
 // ds/dx = -x'/D, ds/dy = -y'/D, ds/dphi = -(x' y - x y')/D,
 // ds/dipt = -kq (x' dx'/domega + y' dy'/domega)/D, ds/dz = ds/dtheta = 0.
-// d: the step finish_crossing applied after the last helix evaluation (the
-// displacements x' - x = chord cos(phi_m), y' - y = chord sin(phi_m) move by
-// -d (cos phi', sin phi')).
+// dxp, dyp: the displacements x' - x and y' - y (chord cos(phi_m) and
+// chord sin(phi_m) at the last helix evaluation, moved by the step
+// finish_crossing applied).
 template <typename T>
 __device__ __forceinline__ void jacobian_cylinder(T x, T y, T w, T kq, T s, T cot,
-                                                  T sinth, const HelixT<T>& h, JacT<T>& J, T d = T(0)) {
+                                                  T sinth, const HelixT<T>& h, JacT<T>& J, T dxp, T dyp) {
     T hs2 = T(0.5) * s * s;
-    const T dxp = fma_(-d, h.cp, h.chord * h.cm);    // x' - x
-    const T dyp = fma_(-d, h.sp, h.chord * h.sm);    // y' - y
     T dxw = hs2 * (h.dS * h.cm - h.S * h.sm);
     T dyw = hs2 * (h.dS * h.sm + h.S * h.cm);
     T iD = rcp_(h.x * h.cp + h.y * h.sp);
@@ -493,25 +571,41 @@ __device__ __forceinline__ void transport(const JacT<T>& J, T* c) {
 }
 
 // ----------------------------------------------------------- Kalman update
-// 3x3 symmetric inverse by cofactors, with the positive-definiteness test
-// on the leading minors (equivalent to Cholesky pivots d_k > tau S_kk):
-//   S00 > 0,  m2 = S00 S11 - S10^2 > tau S00 S11,  det > tau S22 m2.
-
+// 3x3 symmetric inverse through S = L D L^T (L unit lower triangular),
+// S^-1 = L^-T D^-1 L^-1, with the positive-definiteness test on the pivots:
+//   d0 = S00 > 0,  d1 = S11 - S10^2 / S00 > tau S11,  d2 > tau S22.
+// Each pivot comes from one subtraction from a diagonal element, so it keeps
+// its accuracy when S is ill-conditioned -- a large prior variance along the
+// surface (a track crossing at a shallow angle) against a precise hit --
+// where the cofactor form loses digits twice, in the 2x2 minors and again in
+// the determinant, and the Joseph update then turns that error of S^-1 into
+// one of the posterior covariance larger by the ratio of prior to posterior
+// variance.
 template <typename T>
 __device__ __forceinline__ bool inv3_spd(const T s[6], T inv[6], T tau) {
     // s: packed (00, 10, 11, 20, 21, 22)
-    T c00 = s[2] * s[5] - s[4] * s[4];
-    T c10 = s[4] * s[3] - s[1] * s[5];
-    T c11 = s[0] * s[5] - s[3] * s[3];
-    T c20 = s[1] * s[4] - s[2] * s[3];
-    T c21 = s[3] * s[1] - s[0] * s[4];
-    T c22 = s[0] * s[2] - s[1] * s[1];
-    T det = s[0] * c00 + s[1] * c10 + s[3] * c20;
-    bool ok = (s[0] > T(0)) && (c22 > tau * s[0] * s[2]) && (det > tau * s[5] * c22);
+    const T d0 = s[0];
+    const T i0 = rcp_(d0);
+    const T l10 = s[1] * i0, l20 = s[3] * i0;
+    const T d1 = fma_(-l10, s[1], s[2]);
+    const T e21 = fma_(-l20, s[1], s[4]);
+    const T i1 = rcp_(d1);
+    const T l21 = e21 * i1;
+    const T d2 = fma_(-l21, e21, fma_(-l20, s[3], s[5]));
+    const bool ok = (d0 > T(0)) && (d1 > tau * s[2]) && (d2 > tau * s[5]);
     if (!ok) return false;
-    T id = rcp_(det);
-    inv[0] = c00 * id; inv[1] = c10 * id; inv[2] = c11 * id;
-    inv[3] = c20 * id; inv[4] = c21 * id; inv[5] = c22 * id;
+    const T i2 = rcp_(d2);
+    // L^-1 = [[1, 0, 0], [-l10, 1, 0], [l10 l21 - l20, -l21, 1]]
+    const T m20 = fma_(l10, l21, -l20);
+    const T t20 = m20 * i2;                  // (S^-1)_20
+    const T t21 = -l21 * i2;                 // (S^-1)_21
+    const T v10 = -l10 * i1;
+    inv[5] = i2;
+    inv[4] = t21;
+    inv[3] = t20;
+    inv[2] = fma_(-l21, t21, i1);
+    inv[1] = fma_(-l21, t20, v10);
+    inv[0] = fma_(m20, t20, fma_(-l10, v10, i0));
     return true;
 }
 
@@ -522,11 +616,12 @@ __device__ __forceinline__ bool inv3_spd(const T s[6], T inv[6], T tau) {
 // covariance in FP64.  Kept out of line, with loops over small arrays, so its
 // registers do not weigh on the FP32 path that runs almost always.
 struct Fp64Io {
-    float p[6], c[21], m[3], V[6], chi2;
+    double p[6];   // the state's parameters with their low parts
+    float c[21], m[3], V[6], chi2;
 };
 
 __device__ __noinline__ uint32_t kalman_update_fp64(Fp64Io* io, float chi2_cut) {
-    float* p = io->p;
+    double* p = io->p;
     float* c = io->c;
     const float* m = io->m;
     const float* V = io->V;
@@ -546,7 +641,7 @@ __device__ __noinline__ uint32_t kalman_update_fp64(Fp64Io* io, float chi2_cut) 
     double Sm[3][3] = {{Si[0], Si[1], Si[3]}, {Si[1], Si[2], Si[4]}, {Si[3], Si[4], Si[5]}};
     double r[3], w[3], c2 = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < 3; ++i) r[i] = (double)m[i] - (double)p[i];
+    for (int i = 0; i < 3; ++i) r[i] = (double)m[i] - p[i];
 #pragma unroll 1
     for (int i = 0; i < 3; ++i) {
         w[i] = Sm[i][0] * r[0] + Sm[i][1] * r[1] + Sm[i][2] * r[2];
@@ -562,7 +657,7 @@ __device__ __noinline__ uint32_t kalman_update_fp64(Fp64Io* io, float chi2_cut) 
             K[i][j] = C[i][0] * Sm[0][j] + C[i][1] * Sm[1][j] + C[i][2] * Sm[2][j];
             dp += C[i][j] * w[j];
         }
-        p[i] = (float)((double)p[i] + dp);
+        p[i] += dp;
     }
 #pragma unroll 1
     for (int i = 0; i < 6; ++i)
@@ -635,7 +730,7 @@ __device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], c
                 // state itself never has its address taken and stays in registers
                 Fp64Io io;
 #pragma unroll
-                for (int k = 0; k < 6; ++k) io.p[k] = st.p[k];
+                for (int k = 0; k < 6; ++k) io.p[k] = (double)st.p[k] + (double)st.lo[k];
 #pragma unroll
                 for (int k = 0; k < 21; ++k) io.c[k] = st.c[k];
 #pragma unroll
@@ -645,7 +740,10 @@ __device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], c
                 io.chi2 = (float)chi2;
                 res = kalman_update_fp64(&io, P.chi2_cut);
 #pragma unroll
-                for (int k = 0; k < 6; ++k) st.p[k] = io.p[k];
+                for (int k = 0; k < 6; ++k) {
+                    st.p[k] = (float)io.p[k];
+                    st.lo[k] = k == 3 ? 0.0f : (float)(io.p[k] - (double)st.p[k]);
+                }
 #pragma unroll
                 for (int k = 0; k < 21; ++k) st.c[k] = io.c[k];
                 chi2 = io.chi2;
@@ -660,7 +758,7 @@ __device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], c
             }
         }
     }
-    T r0 = m[0] - st.p[0], r1 = m[1] - st.p[1], r2 = m[2] - st.p[2];
+    T r0 = residual_of(st, 0, m[0]), r1 = residual_of(st, 1, m[1]), r2 = residual_of(st, 2, m[2]);
     T w0 = Si[0] * r0 + Si[1] * r1 + Si[3] * r2;
     T w1 = Si[1] * r0 + Si[2] * r1 + Si[4] * r2;
     T w2 = Si[3] * r0 + Si[4] * r1 + Si[5] * r2;
@@ -684,7 +782,9 @@ __device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], c
         KV[i][0] = K[i][0] * V[0] + K[i][1] * V[1] + K[i][2] * V[3];
         KV[i][1] = K[i][0] * V[1] + K[i][1] * V[2] + K[i][2] * V[4];
         KV[i][2] = K[i][0] * V[3] + K[i][1] * V[4] + K[i][2] * V[5];
-        st.p[i] = fma_(p0, w0, fma_(p1, w1, fma_(p2, w2, st.p[i])));
+        const T dp = fma_(p0, w0, fma_(p1, w1, p2 * w2));
+        if (i == 3) st.p[i] += dp;
+        else add_to(st, i, dp);
     }
     // M = A C' (entries (i, l) with l <= i, and (i, j) with j < 3)
     auto Mv = [&](int i, int l) -> T {
@@ -740,7 +840,8 @@ __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3]
                                                      const Params& P, T& chi2, uint32_t& flags);
 
 struct Fp64Io2 {
-    float p[6], c[21], m[3], V[6], chi2;
+    double p[6];   // the state's parameters with their low parts
+    float c[21], m[3], V[6], chi2;
 };
 
 // FP64 inverse of the 2x2 S (fallback mode 1), out of line like the full
@@ -796,7 +897,7 @@ __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3]
             if (P.fp64_fallback != 1) {
                 Fp64Io2 io;
 #pragma unroll
-                for (int k = 0; k < 6; ++k) io.p[k] = (float)st.p[k];
+                for (int k = 0; k < 6; ++k) io.p[k] = (double)st.p[k] + (double)st.lo[k];
 #pragma unroll
                 for (int k = 0; k < 21; ++k) io.c[k] = (float)st.c[k];
 #pragma unroll
@@ -806,7 +907,10 @@ __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3]
                 io.chi2 = (float)chi2;
                 res = kalman_update_2d_fp64(&io, P.chi2_cut);
 #pragma unroll
-                for (int k = 0; k < 6; ++k) st.p[k] = io.p[k];
+                for (int k = 0; k < 6; ++k) {
+                    st.p[k] = (float)io.p[k];
+                    st.lo[k] = k == 3 ? T(0) : (T)(io.p[k] - (double)st.p[k]);
+                }
 #pragma unroll
                 for (int k = 0; k < 21; ++k) st.c[k] = io.c[k];
                 chi2 = io.chi2;
@@ -828,9 +932,9 @@ __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3]
         P1[i] = c[I21(i, 2)];
     }
     // residual in the hit frame from the position differences
-    const T dx = m[0] - st.p[0], dy = m[1] - st.p[1];
+    const T dx = residual_of(st, 0, m[0]), dy = residual_of(st, 1, m[1]);
     const T r0 = fma_(-sh, dx, ch * dy);
-    const T r1 = m[2] - st.p[2];
+    const T r1 = residual_of(st, 2, m[2]);
     T w0 = fma_(Si00, r0, Si01 * r1);
     T w1 = fma_(Si01, r0, Si11 * r1);
     const T c2 = fma_(r0, w0, r1 * w1);
@@ -849,7 +953,9 @@ __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3]
         K1[i] = fma_(P0[i], Si01, P1[i] * Si11);
         KV0[i] = fma_(K0[i], v00, K1[i] * v01);
         KV1[i] = fma_(K0[i], v01, K1[i] * v11);
-        st.p[i] = fma_(P0[i], w0, fma_(P1[i], w1, st.p[i]));
+        const T dp = fma_(P0[i], w0, P1[i] * w1);
+        if (i == 3) st.p[i] += dp;
+        else add_to(st, i, dp);
     }
     // M = A C' = C' - K P^T (entries (i, l) with l <= i, and l < 3)
     T M[6][6];
@@ -876,7 +982,7 @@ __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3]
 
 __device__ __noinline__ uint32_t kalman_update_2d_fp64(Fp64Io2* io, float chi2_cut) {
     StateT<double> sd;
-    for (int k = 0; k < 6; ++k) sd.p[k] = io->p[k];
+    for (int k = 0; k < 6; ++k) sd.p[k] = io->p[k];   // already with the low parts
     for (int k = 0; k < 21; ++k) sd.c[k] = io->c[k];
     sd.q = 0.0;
     double m[3], V[6];
@@ -887,7 +993,7 @@ __device__ __noinline__ uint32_t kalman_update_2d_fp64(Fp64Io2* io, float chi2_c
     double c2 = io->chi2;
     uint32_t fl = 0;
     const uint32_t r = kalman_update_2d<double>(sd, m, V, Pd, c2, fl);
-    for (int k = 0; k < 6; ++k) io->p[k] = (float)sd.p[k];
+    for (int k = 0; k < 6; ++k) io->p[k] = sd.p[k];
     for (int k = 0; k < 21; ++k) io->c[k] = (float)sd.c[k];
     io->chi2 = (float)c2;
     return r;
@@ -902,6 +1008,26 @@ __device__ __forceinline__ T wrap_phi(T a) {
     if (!(fabs(r) <= T(3.0) * pi_<T>())) r = a - two_pi_<T>() * floor((a + pi_<T>()) * T(0.159154943091895336));
     r = r > pi_<T>() ? r - two_pi_<T>() : r;
     return r <= -pi_<T>() ? r + two_pi_<T>() : r;
+}
+
+// The same on the state's phi with its low part: 2 pi is subtracted in two
+// parts (its float and the remainder), branch-free for the usual one step.
+constexpr float TWO_PI_HI = 6.28318548202514648f;          // float(2 pi)
+constexpr float TWO_PI_LO = -1.74845553146e-07f;            // 2 pi - TWO_PI_HI
+template <typename T>
+__device__ __forceinline__ void wrap_phi_state(StateT<T>& st) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (!(fabsf(st.p[4]) <= 3.0f * PI_F)) {           // far outside: plain reduction
+            st.p[4] = wrap_phi(st.p[4] + st.lo[4]);
+            st.lo[4] = 0.0f;
+        }
+        const float a = st.p[4];
+        const float k = a > PI_F ? -1.0f : (a <= -PI_F ? 1.0f : 0.0f);
+        add_to(st, 4, k * TWO_PI_HI);
+        st.lo[4] = fmaf(k, TWO_PI_LO, st.lo[4]);
+    } else {
+        st.p[4] = wrap_phi(st.p[4]);
+    }
 }
 
 template <typename T>
@@ -945,7 +1071,7 @@ __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3
     if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
     T x = st.p[0], y = st.p[1];
     T sphi, cphi;
-    sincos_(st.p[4], &sphi, &cphi);
+    sincos_comp(st, 4, &sphi, &cphi);
     T kq = -st.q * T(2.99792458e-3) * P.bz;
     T w = kq * st.p[3];
     if (!cylinder_reachable(x, y, cphi, sphi, w, R)) { o.flags = ST_NO_CROSSING; return o; }
@@ -986,14 +1112,18 @@ __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3
     }
     const T dapp = finish_crossing(w, ds, s, h);
     T sinth, costh;
-    sincos_(st.p[5], &sinth, &costh);
+    sincos_comp(st, 5, &sinth, &costh);
     T cot = div_(costh, sinth);
+    // displacement of the crossing from the start, x' - x = chord cos(phi_m),
+    // moved by the step finish_crossing applied
+    const T dxp = fma_(-dapp, h.cp, h.chord * h.cm);
+    const T dyp = fma_(-dapp, h.sp, h.chord * h.sm);
     JacT<T> J;
-    jacobian_cylinder(x, y, w, kq, s, cot, sinth, h, J, dapp);
-    st.p[0] = h.x;
-    st.p[1] = h.y;
-    st.p[2] = fma_(s, cot, st.p[2]);
-    st.p[4] = st.p[4] + T(2.0) * h.u;
+    jacobian_cylinder(x, y, w, kq, s, cot, sinth, h, J, dxp, dyp);
+    add_to(st, 0, dxp);
+    add_to(st, 1, dyp);
+    add_to(st, 2, s * cot);
+    add_to(st, 4, T(2.0) * h.u);
     transport<0>(J, st.c);
     if constexpr (!UPDATE) {
         o.updated = true;
@@ -1004,7 +1134,8 @@ __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3
     else u = kalman_update(st, m, V, P, chi2, o.flags);
     o.flags |= u;
     o.updated = (u == 0);
-    st.p[4] = wrap_phi(st.p[4]);
+    wrap_phi_state(st);
+    renormalise(st);
     return o;
 }
 
@@ -1015,22 +1146,23 @@ __device__ __forceinline__ StepOut step_plane(StateT<T>& st, T Z, const T m[3], 
     StepOut o{0u, false, 0};
     if (!finite3(m)) { o.flags = ST_HIT_MISSING; return o; }
     T sinth, costh;
-    sincos_(st.p[5], &sinth, &costh);
+    sincos_comp(st, 5, &sinth, &costh);
     T tanth = div_(sinth, costh);
-    T s = (Z - st.p[2]) * tanth;     // ahead (or at most T(BACK_TOL) behind), within half a turn
+    T s = residual_of(st, 2, Z) * tanth;     // ahead (or at most T(BACK_TOL) behind), within half a turn
     T kq = -st.q * T(2.99792458e-3) * P.bz;
     T w = kq * st.p[3];
     if (!(s > -T(BACK_TOL)) || !(fabs(w * s) <= pi_<T>())) { o.flags = ST_NO_CROSSING; return o; }
     T sphi, cphi;
-    sincos_(st.p[4], &sphi, &cphi);
+    sincos_comp(st, 4, &sphi, &cphi);
     HelixT<T> h;
     helix_at(st.p[0], st.p[1], cphi, sphi, w, s, h);
     JacT<T> J;
     jacobian_plane(w, kq, s, tanth, sinth, costh, h, J);
-    st.p[0] = h.x;
-    st.p[1] = h.y;
+    add_to(st, 0, h.chord * h.cm);
+    add_to(st, 1, h.chord * h.sm);
     st.p[2] = Z;
-    st.p[4] = st.p[4] + T(2.0) * h.u;
+    st.lo[2] = T(0);
+    add_to(st, 4, T(2.0) * h.u);
     transport<1>(J, st.c);
     if constexpr (!UPDATE) {
         o.updated = true;
@@ -1039,7 +1171,8 @@ __device__ __forceinline__ StepOut step_plane(StateT<T>& st, T Z, const T m[3], 
     uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
     o.flags |= u;
     o.updated = (u == 0);
-    st.p[4] = wrap_phi(st.p[4]);
+    wrap_phi_state(st);
+    renormalise(st);
     return o;
 }
 
@@ -1050,7 +1183,8 @@ __device__ __forceinline__ void update_step(StateT<T>& st, const T m[3], const T
     const uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
     o.flags |= u;
     o.updated = (u == 0);
-    st.p[4] = wrap_phi(st.p[4]);
+    wrap_phi_state(st);
+    renormalise(st);
 }
 
 // Newton tolerance for a cylinder of radius R: max(tol, 2 ulp(R)).

@@ -203,7 +203,11 @@ def test_fp64_fallback_triggers_on_ill_conditioned_S(ctx):
         rel = dpar / np.maximum(np.abs(r["par"]), [1, 1, 1, 1e-30, 1, 1e-30])
         errs[name] = (rel.max(), (np.abs(x["chi2"] - r["chi2"]) / np.maximum(r["chi2"], 1)).max())
         print(name, "max rel par %.2e  max rel chi2 %.2e" % errs[name], flush=True)
+    # measured: full FP64 update 2.0e-4 (par) / 5.5e-3 (chi2), FP64 inverse only
+    # 3.5e-4 / 9.7e-3; the full update, the default, is the more accurate
     assert errs["full FP64 update"][0] < 1e-3 and errs["full FP64 update"][1] < 1e-2
+    assert errs["FP64 inverse only"][0] < 1e-3 and errs["FP64 inverse only"][1] < 2e-2
+    assert errs["full FP64 update"][1] <= errs["FP64 inverse only"][1]
 
 
 def test_empty_and_argument_errors(ctx):
