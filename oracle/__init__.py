@@ -54,8 +54,8 @@ def lib():
         L.orc_update.restype = C.c_uint32
         L.orc_update_2d.argtypes = [dp, dp, dp, dp, C.c_double, dp, dp, dp]
         L.orc_update_2d.restype = C.c_uint32
-        L.orc_fit.argtypes = [C.c_int64] + [C.c_void_p] * 8 + [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int] \
-            + [C.c_void_p] * 8
+        L.orc_fit.argtypes = [C.c_int64] + [C.c_void_p] * 8 + [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                                               C.c_int] + [C.c_void_p] * 8
         L.orc_fit.restype = None
         L.orc_disk_sign.argtypes = [C.c_double]
         L.orc_disk_sign.restype = C.c_double
@@ -116,11 +116,21 @@ def update_2d(p, C6, m, V21, chi2_cut=0.0):
 
 
 # ------------------------------------------------------------------ batches
+SENS_RUNS = 4   # conditioning-measurement runs: round to nearest + 3 random-rounding seeds
+
+
 def fit(par, cov, q, offsets, stype, sval, hits, hitcov, bz=3.8, chi2_cut=0.0, form=0,
-        nthreads=0, layers=False, update_2d=False):
+        nthreads=0, layers=False, update_2d=False, sensitivity=True, round32=0):
     """Per-track fit over CSR surface lists; returns a dict of outputs.
 
-    update_2d: cylinders take the update in the hit's (r-phi, z) frame."""
+    update_2d: cylinders take the update in the hit's (r-phi, z) frame.
+    round32 (0: the exact FP64 fit): the fit as an FP32 implementation
+    computes it -- stored values, the matrix algebra and the cylinder
+    crossing rounded to FP32 -- with round-to-nearest (1) or random rounding
+    seeded by the value (>= 2).  sensitivity: also run SENS_RUNS such fits
+    (modes 1 .. SENS_RUNS) and return their outputs as a list under
+    "f32_runs" (the first also as "f32"): how far FP32 rounding moves each
+    track's result, which the parity rule uses as the track's conditioning."""
     par, cov, q = _f64(par), _f64(cov), _f64(q)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     stype = np.ascontiguousarray(stype, dtype=np.uint8)
@@ -138,9 +148,14 @@ def fit(par, cov, q, offsets, stype, sval, hits, hitcov, bz=3.8, chi2_cut=0.0, f
     lp = [vp(out[k]) if layers else None for k in ("lay_par", "lay_cov", "lay_chi2")] if layers \
         else [None, None, None]
     lib().orc_fit(n, vp(par), vp(cov), vp(q), vp(offsets), vp(stype), vp(sval), vp(hits), vp(hitcov),
-                  float(bz), float(chi2_cut), int(form), int(bool(update_2d)), int(nthreads),
+                  float(bz), float(chi2_cut), int(form), int(bool(update_2d)), int(round32), int(nthreads),
                   vp(out["par"]), vp(out["cov"]), vp(out["chi2"]), vp(out["nused"]), vp(out["status"]),
                   *lp)
+    if sensitivity and not round32:
+        out["f32_runs"] = [fit(par, cov, q, offsets, stype, sval, hits, hitcov, bz=bz, chi2_cut=chi2_cut,
+                               form=form, nthreads=nthreads, update_2d=update_2d, sensitivity=False, round32=k)
+                           for k in range(1, SENS_RUNS + 1)]
+        out["f32"] = out["f32_runs"][0]
     return out
 
 

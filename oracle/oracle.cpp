@@ -26,6 +26,7 @@
 // State p = (x, y, z, 1/pT, phi, theta); charge q = +-1 separate.
 // Curvature omega = -q * KAPPA * B * (1/pT) [1/cm]; s = transverse arc length.
 // Covariances are packed lower-triangle row-major: idx(i,j) = i(i+1)/2 + j.
+#include <cfloat>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -94,6 +95,33 @@ inline Dual atan2(const Dual& y, const Dual& x) {
     return r;
 }
 using std::sin; using std::cos; using std::sqrt; using std::acos; using std::asin; using std::atan2; using std::fabs;
+
+// ------------------------------------------- FP32 rounding (measurement)
+// The conditioning-measurement mode of fit_one (round32 > 0) redoes the fit
+// as an FP32 implementation would, rounding values to FP32.  mode 1: round
+// to nearest.  mode k >= 2: random rounding -- each value goes to one of
+// its two neighbouring FP32 numbers with equal probability, drawn from a
+// splitmix64 stream seeded by k and the track -- the random-rounding
+// arithmetic of the CESTAC method (Vignes): the spread of the results over
+// a few such runs estimates how many of their digits FP32 rounding leaves.
+struct Rounder {
+    int mode;
+    uint64_t state;
+    uint64_t next() {                      // splitmix64 (Steele, Lea, Flood 2014)
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }   // [0, 1)
+    double operator()(double v) {
+        const float f = (float)v;
+        if (mode == 1 || !std::isfinite(v) || (double)f == v) return f;
+        const float g = (double)f < v ? std::nextafter(f, INFINITY) : std::nextafter(f, -INFINITY);
+        return (next() >> 63) ? f : g;
+    }
+};
+inline double rr(Rounder* rd, double v) { return rd ? (*rd)(v) : v; }
 
 // a constant of the arithmetic type in use (zero derivative for duals)
 template <class T> inline T mk(double v) { return T(v); }
@@ -214,11 +242,36 @@ bool path_to_surface(const T p[6], double q, double bz, int type, double v, T* s
 // Propagate p to the surface; fills the new state and (optionally) the 6x6
 // Jacobian J[i*6+j] = d p'_i / d p_j and the path length.  Returns false if
 // the surface is not reached.
+//
+// r32 (the conditioning-measurement mode of fit_one, cylinders only): an
+// FP32 fit finds the crossing as a root of the constraint (r(s)^2 - R^2) / 2R
+// evaluated in FP32, whose rounding error is of order FLT_EPSILON R; its
+// crossing therefore lies about FLT_EPSILON R / cos(incidence) along the
+// track from the exact one (at most 0.1 cm), and its path-length
+// derivatives are those of the implicit function ds/dp = -(dg/dp) / (dg/ds)
+// at that point rather than at the root.  The crossing is moved by that
+// amount (in random rounding, by a uniform random fraction of it either
+// way) and the derivatives are formed there.
 bool propagate(const double p[6], double q, double bz, int type, double v,
-               double pout[6], double* J, double* s_out) {
+               double pout[6], double* J, double* s_out, Rounder* r32 = nullptr) {
     Dual pd[6], sd, od[6];
     for (int j = 0; j < 6; ++j) pd[j] = var(p[j], j);
     if (!path_to_surface(pd, q, bz, type, v, &sd)) return false;
+    if (r32 && type == 0) {
+        Dual h0[6];
+        helix(pd, q, bz, sd, h0);
+        const double D0 = h0[0].v * std::cos(h0[4].v) + h0[1].v * std::sin(h0[4].v);   // R cos(incidence)
+        double shift = (double)FLT_EPSILON * v * v / std::max(std::fabs(D0), 1e-300);
+        shift = std::min(shift, 0.1);
+        if (r32->mode > 1) shift *= 2.0 * r32->uniform() - 1.0;   // random size and side
+        Dual hf[6];
+        const Dual sf = cst(sd.v + shift);
+        helix(pd, q, bz, sf, hf);
+        const Dual g = (hf[0] * hf[0] + hf[1] * hf[1]) * (0.5 / v);     // dg/dp at fixed s
+        const double gs = (hf[0].v * std::cos(hf[4].v) + hf[1].v * std::sin(hf[4].v)) / v;   // dg/ds
+        sd = sf;
+        for (int j = 0; j < 6; ++j) sd.d[j] = -g.d[j] / gs;
+    }
     helix(pd, q, bz, sd, od);
     for (int i = 0; i < 6; ++i) {
         pout[i] = od[i].v;
@@ -236,13 +289,21 @@ void unpack(const double* c21, double C[36]) {
 void pack(const double C[36], double* c21) {
     for (int i = 0; i < 6; ++i) for (int j = 0; j <= i; ++j) c21[ix(i, j)] = 0.5 * (C[i * 6 + j] + C[j * 6 + i]);
 }
-// generic dense product: R[m x n] = A[m x k] * B[k x n] (B given with its row stride)
-void matmul(const double* A, const double* B, double* R, int m, int k, int n) {
+// generic dense product: R[m x n] = A[m x k] * B[k x n] (B given with its row stride).
+// rd: operands, products and sums rounded to FP32 (the conditioning-
+// measurement mode of fit_one), else FP64.
+void matmul(const double* A, const double* B, double* R, int m, int k, int n, Rounder* rd = nullptr) {
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < n; ++j) {
-            double a = 0.0;
-            for (int l = 0; l < k; ++l) a += A[i * k + l] * B[l * n + j];
-            R[i * n + j] = a;
+            if (rd) {
+                double a = 0.0;
+                for (int l = 0; l < k; ++l) a = (*rd)(a + (*rd)((*rd)(A[i * k + l]) * (*rd)(B[l * n + j])));
+                R[i * n + j] = a;
+            } else {
+                double a = 0.0;
+                for (int l = 0; l < k; ++l) a += A[i * k + l] * B[l * n + j];
+                R[i * n + j] = a;
+            }
         }
 }
 void transpose(const double* A, double* T, int m, int n) {
@@ -251,31 +312,65 @@ void transpose(const double* A, double* T, int m, int n) {
 
 // Cholesky of a symmetric 3x3 and its inverse.  Not PD when a pivot is
 // <= PD_TAU times the corresponding diagonal element (or not finite).
-bool inverse_spd3(const double S[9], double Sinv[9]) {
-    double L[9] = {0};
+template <class F>
+bool inverse_spd3_t(const F S[9], F Sinv[9]) {
+    F L[9] = {0};
     for (int j = 0; j < 3; ++j) {
-        double dsum = S[j * 3 + j];
+        F dsum = S[j * 3 + j];
         for (int k = 0; k < j; ++k) dsum -= L[j * 3 + k] * L[j * 3 + k];
         if (!(dsum > PD_TAU * S[j * 3 + j]) || !std::isfinite(dsum)) return false;
         L[j * 3 + j] = std::sqrt(dsum);
         for (int i = j + 1; i < 3; ++i) {
-            double a = S[i * 3 + j];
+            F a = S[i * 3 + j];
             for (int k = 0; k < j; ++k) a -= L[i * 3 + k] * L[j * 3 + k];
             L[i * 3 + j] = a / L[j * 3 + j];
         }
     }
     // S^-1 column by column: solve L L^T x = e_c
     for (int c = 0; c < 3; ++c) {
-        double y[3], x[3];
+        F y[3], x[3];
         for (int i = 0; i < 3; ++i) {
-            double a = (i == c) ? 1.0 : 0.0;
+            F a = (i == c) ? F(1) : F(0);
             for (int k = 0; k < i; ++k) a -= L[i * 3 + k] * y[k];
             y[i] = a / L[i * 3 + i];
         }
         for (int i = 2; i >= 0; --i) {
-            double a = y[i];
+            F a = y[i];
             for (int k = i + 1; k < 3; ++k) a -= L[k * 3 + i] * x[k];
             x[i] = a / L[i * 3 + i];
+        }
+        for (int i = 0; i < 3; ++i) Sinv[i * 3 + c] = x[i];
+    }
+    return true;
+}
+// rd: every operation of the factorisation and the solves rounded to FP32
+// (conditioning-measurement mode), else the FP64 routine above.
+bool inverse_spd3(const double S[9], double Sinv[9], Rounder* rd = nullptr) {
+    if (!rd) return inverse_spd3_t<double>(S, Sinv);
+    Rounder& R = *rd;
+    double L[9] = {0};
+    for (int j = 0; j < 3; ++j) {
+        double dsum = R(S[j * 3 + j]);
+        for (int k = 0; k < j; ++k) dsum = R(dsum - R(L[j * 3 + k] * L[j * 3 + k]));
+        if (!(dsum > PD_TAU * S[j * 3 + j]) || !std::isfinite(dsum)) return false;
+        L[j * 3 + j] = R(std::sqrt(dsum));
+        for (int i = j + 1; i < 3; ++i) {
+            double a = R(S[i * 3 + j]);
+            for (int k = 0; k < j; ++k) a = R(a - R(L[i * 3 + k] * L[j * 3 + k]));
+            L[i * 3 + j] = R(a / L[j * 3 + j]);
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        double y[3], x[3];
+        for (int i = 0; i < 3; ++i) {
+            double a = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) a = R(a - R(L[i * 3 + k] * y[k]));
+            y[i] = R(a / L[i * 3 + i]);
+        }
+        for (int i = 2; i >= 0; --i) {
+            double a = y[i];
+            for (int k = i + 1; k < 3; ++k) a = R(a - R(L[k * 3 + i] * x[k]));
+            x[i] = R(a / L[i * 3 + i]);
         }
         for (int i = 0; i < 3; ++i) Sinv[i * 3 + c] = x[i];
     }
@@ -289,12 +384,19 @@ inline double wrap_phi(double a) {
     return r;
 }
 
+// FP32 rounding of an intermediate array, in the conditioning-measurement
+// mode only (rd set); a no-op otherwise.
+inline void rnd32(double* a, int n, Rounder* rd) {
+    if (rd) for (int i = 0; i < n; ++i) a[i] = (*rd)(a[i]);
+}
+
 // ------------------------------------------------------ O6: Kalman update
 // form 0: Joseph  C+ = (I-KH) C' (I-KH)^T + K V K^T
 // form 1: standard C+ = (I-KH) C'
 // Returns 0 updated, ST_S_NOT_PD or ST_CHI2_CUT when skipped.
 uint32_t kalman_update(const double p[6], const double C[36], const double m[3], const double V21[6],
-                       int form, double chi2_cut, double pout[6], double Cout[36], double* chi2) {
+                       int form, double chi2_cut, double pout[6], double Cout[36], double* chi2,
+                       Rounder* r32 = nullptr) {
     double V[9];
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) {
         int a = i > j ? i : j, b = i > j ? j : i;
@@ -302,16 +404,21 @@ uint32_t kalman_update(const double p[6], const double C[36], const double m[3],
     }
     double S[9], Sinv[9];
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) S[i * 3 + j] = C[i * 6 + j] + V[i * 3 + j];
-    if (!inverse_spd3(S, Sinv)) return ST_S_NOT_PD;
+    rnd32(S, 9, r32);
+    if (!inverse_spd3(S, Sinv, r32)) return ST_S_NOT_PD;
+    rnd32(Sinv, 9, r32);
     double r[3];
     for (int i = 0; i < 3; ++i) r[i] = m[i] - p[i];
+    rnd32(r, 3, r32);
     double c2 = 0.0;
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) c2 += r[i] * Sinv[i * 3 + j] * r[j];
+    rnd32(&c2, 1, r32);
     if (chi2_cut > 0.0 && c2 > chi2_cut) return ST_CHI2_CUT;
     // K = C' H^T S^-1 ; C' H^T = first three columns of C'
     double PHt[18], K[18];
     for (int i = 0; i < 6; ++i) for (int j = 0; j < 3; ++j) PHt[i * 3 + j] = C[i * 6 + j];
-    matmul(PHt, Sinv, K, 6, 3, 3);
+    matmul(PHt, Sinv, K, 6, 3, 3, r32);
+    rnd32(K, 18, r32);
     for (int i = 0; i < 6; ++i) {
         double a = 0.0;
         for (int j = 0; j < 3; ++j) a += K[i * 3 + j] * r[j];
@@ -324,17 +431,21 @@ uint32_t kalman_update(const double p[6], const double C[36], const double m[3],
         A[i * 6 + j] = (i == j ? 1.0 : 0.0) - (j < 3 ? K[i * 3 + j] : 0.0);
     }
     double AC[36];
-    matmul(A, C, AC, 6, 6, 6);
+    rnd32(A, 36, r32);
+    matmul(A, C, AC, 6, 6, 6, r32);
+    rnd32(AC, 36, r32);
     if (form == 1) {
         for (int i = 0; i < 36; ++i) Cout[i] = AC[i];
     } else {
         double At[36], ACAt[36], KV[18], Kt[18], KVKt[36];
         transpose(A, At, 6, 6);
-        matmul(AC, At, ACAt, 6, 6, 6);
-        matmul(K, V, KV, 6, 3, 3);
+        matmul(AC, At, ACAt, 6, 6, 6, r32);
+        matmul(K, V, KV, 6, 3, 3, r32);
+        rnd32(KV, 18, r32);
         transpose(K, Kt, 6, 3);
-        matmul(KV, Kt, KVKt, 6, 3, 6);
+        matmul(KV, Kt, KVKt, 6, 3, 6, r32);
         for (int i = 0; i < 36; ++i) Cout[i] = ACAt[i] + KVKt[i];
+        rnd32(Cout, 36, r32);
     }
     // symmetrise
     for (int i = 0; i < 6; ++i) for (int j = 0; j < i; ++j) {
@@ -355,7 +466,8 @@ uint32_t kalman_update(const double p[6], const double C[36], const double m[3],
 // K = C' H^T S^-1, p+ = p' + K r, Joseph C+ = (I-KH) C' (I-KH)^T + K V2 K^T,
 // chi2 = r^T S^-1 r (two degrees of freedom).
 uint32_t kalman_update_2d(const double p[6], const double C[36], const double m[3], const double V21[6],
-                          double chi2_cut, double pout[6], double Cout[36], double* chi2) {
+                          double chi2_cut, double pout[6], double Cout[36], double* chi2,
+                          Rounder* r32 = nullptr) {
     const double rh = std::hypot(m[0], m[1]);
     if (!(rh > 0.0)) return ST_S_NOT_PD;
     const double c = m[0] / rh, s = m[1] / rh;
@@ -368,14 +480,15 @@ uint32_t kalman_update_2d(const double p[6], const double C[36], const double m[
     }
     const double R[6] = {-s, c, 0.0, 0.0, 0.0, 1.0};
     double RV[6], Rt[6], V2[4];
-    matmul(R, V, RV, 2, 3, 3);
+    matmul(R, V, RV, 2, 3, 3, r32);
     transpose(R, Rt, 2, 3);
-    matmul(RV, Rt, V2, 2, 3, 2);
+    matmul(RV, Rt, V2, 2, 3, 2, r32);
     double Ht[12], CHt[12], S[4];
     transpose(H, Ht, 2, 6);
-    matmul(C, Ht, CHt, 6, 6, 2);
-    matmul(H, CHt, S, 2, 6, 2);
+    matmul(C, Ht, CHt, 6, 6, 2, r32);
+    matmul(H, CHt, S, 2, 6, 2, r32);
     for (int i = 0; i < 4; ++i) S[i] += V2[i];
+    rnd32(S, 4, r32);
     // 2x2 Cholesky with the same pivot rule as the 3x3 one
     const double l00sq = S[0];
     if (!(l00sq > PD_TAU * S[0]) || !std::isfinite(l00sq)) return ST_S_NOT_PD;
@@ -387,23 +500,29 @@ uint32_t kalman_update_2d(const double p[6], const double C[36], const double m[
     matmul(H, p, Hp, 2, 6, 1);
     const double mloc[2] = {-s * m[0] + c * m[1], m[2]};
     for (int i = 0; i < 2; ++i) r[i] = mloc[i] - Hp[i];
+    rnd32(r, 2, r32);
     double c2 = 0.0;
     for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) c2 += r[i] * Sinv[i * 2 + j] * r[j];
     if (chi2_cut > 0.0 && c2 > chi2_cut) return ST_CHI2_CUT;
     double K[12];
-    matmul(CHt, Sinv, K, 6, 2, 2);
+    matmul(CHt, Sinv, K, 6, 2, 2, r32);
+    rnd32(K, 12, r32);
     for (int i = 0; i < 6; ++i) pout[i] = p[i] + K[i * 2] * r[0] + K[i * 2 + 1] * r[1];
     pout[4] = wrap_phi(pout[4]);
     double KH[36], A[36], AC[36], At[36], ACAt[36], KV[12], Kt[12], KVKt[36];
-    matmul(K, H, KH, 6, 2, 6);
+    matmul(K, H, KH, 6, 2, 6, r32);
     for (int i = 0; i < 36; ++i) A[i] = ((i / 6) == (i % 6) ? 1.0 : 0.0) - KH[i];
-    matmul(A, C, AC, 6, 6, 6);
+    rnd32(A, 36, r32);
+    matmul(A, C, AC, 6, 6, 6, r32);
+    rnd32(AC, 36, r32);
     transpose(A, At, 6, 6);
-    matmul(AC, At, ACAt, 6, 6, 6);
-    matmul(K, V2, KV, 6, 2, 2);
+    matmul(AC, At, ACAt, 6, 6, 6, r32);
+    matmul(K, V2, KV, 6, 2, 2, r32);
+    rnd32(KV, 12, r32);
     transpose(K, Kt, 6, 2);
-    matmul(KV, Kt, KVKt, 6, 2, 6);
+    matmul(KV, Kt, KVKt, 6, 2, 6, r32);
     for (int i = 0; i < 36; ++i) Cout[i] = ACAt[i] + KVKt[i];
+    rnd32(Cout, 36, r32);
     for (int i = 0; i < 6; ++i) for (int j = 0; j < i; ++j) {
         double a = 0.5 * (Cout[i * 6 + j] + Cout[j * 6 + i]);
         Cout[i * 6 + j] = Cout[j * 6 + i] = a;
@@ -418,6 +537,7 @@ struct FitArgs {
     const int64_t* offsets; const uint8_t* stype; const double* sval;
     const double* hits; const double* hitcov;
     double bz, chi2_cut; int form; int update_2d;
+    int round32;   // > 0: the conditioning-measurement mode with this rounding (see Rounder)
     double* par_out; double* cov_out; double* chi2_out; int32_t* nused_out; uint32_t* status_out;
     double* lay_par; double* lay_cov; double* lay_chi2;   // nullable per-surface dumps
 };
@@ -430,10 +550,29 @@ bool bad_input(const double* p, const double* c21) {
     return false;
 }
 
+// round32 mode: the fit as an FP32 implementation of the same algorithm
+// computes it -- the state and covariance stored as FP32 between steps, the
+// matrix algebra of the transport (J C J^T) and of the update (S, its
+// Cholesky inverse, K, I - K H, the Joseph products, K V K^T) done in FP32
+// arithmetic -- with the helix and the crossing still evaluated in FP64,
+// from the rounded state, except that a cylinder crossing is located as an
+// FP32 root finder locates it (propagate).  The tests use the mode to
+// measure how far FP32 rounding moves each track's result: the conditioning
+// of that track's fit.  It is large where the update cancels most of the
+// prior covariance (a track crossing its surface at a shallow angle carries
+// a large variance along the surface, which one precise hit removes) and
+// where the transport Jacobian is large.
+void round_to_float(double* p, double* C, Rounder& rd) {
+    for (int i = 0; i < 6; ++i) p[i] = rd(p[i]);
+    for (int i = 0; i < 6; ++i) for (int j = 0; j <= i; ++j) C[i * 6 + j] = C[j * 6 + i] = rd(C[i * 6 + j]);
+}
+
 void fit_one(const FitArgs& a, int64_t t) {
     double p[6], C[36];
     for (int i = 0; i < 6; ++i) p[i] = a.par[t * 6 + i];
     unpack(a.cov + t * 21, C);
+    Rounder rounder{a.round32, ((uint64_t)(uint32_t)a.round32 << 40) ^ (uint64_t)t};
+    Rounder* rd = a.round32 > 0 ? &rounder : nullptr;
     double q = a.q[t];
     uint32_t st = 0;
     double chi2 = 0.0;
@@ -450,22 +589,26 @@ void fit_one(const FitArgs& a, int64_t t) {
                 st |= ST_HIT_MISSING;
             } else {
                 double pp[6], J[36];
-                if (!propagate(p, q, a.bz, a.stype[h], a.sval[h], pp, J, nullptr)) {
+                if (!propagate(p, q, a.bz, a.stype[h], a.sval[h], pp, J, nullptr, rd)) {
                     st |= ST_NO_CROSSING;
                 } else {
                     double JC[36], Jt[36], Cp[36];
-                    matmul(J, C, JC, 6, 6, 6);
+                    rnd32(J, 36, rd);
+                    matmul(J, C, JC, 6, 6, 6, rd);
                     transpose(J, Jt, 6, 6);
-                    matmul(JC, Jt, Cp, 6, 6, 6);
+                    matmul(JC, Jt, Cp, 6, 6, 6, rd);
                     for (int i = 0; i < 6; ++i) for (int j = 0; j < i; ++j) {
                         double v = 0.5 * (Cp[i * 6 + j] + Cp[j * 6 + i]);
                         Cp[i * 6 + j] = Cp[j * 6 + i] = v;
                     }
+                    if (rd) round_to_float(pp, Cp, *rd);
                     double pu[6], Cu[36], c2 = 0.0;
                     uint32_t u = (a.update_2d && a.stype[h] == 0)
-                                     ? kalman_update_2d(pp, Cp, m, a.hitcov + h * 6, a.chi2_cut, pu, Cu, &c2)
-                                     : kalman_update(pp, Cp, m, a.hitcov + h * 6, a.form, a.chi2_cut, pu, Cu, &c2);
+                                     ? kalman_update_2d(pp, Cp, m, a.hitcov + h * 6, a.chi2_cut, pu, Cu, &c2, rd)
+                                     : kalman_update(pp, Cp, m, a.hitcov + h * 6, a.form, a.chi2_cut, pu, Cu, &c2,
+                                                     rd);
                     if (u == 0) {
+                        if (rd) round_to_float(pu, Cu, *rd);
                         std::memcpy(p, pu, sizeof p);
                         std::memcpy(C, Cu, sizeof C);
                         chi2 += c2;
@@ -536,10 +679,10 @@ uint32_t orc_update_2d(const double p[6], const double C36[36], const double m[3
 void orc_fit(int64_t n, const double* par, const double* cov, const double* q,
              const int64_t* offsets, const uint8_t* stype, const double* sval,
              const double* hits, const double* hitcov, double bz, double chi2_cut, int form,
-             int update_2d, int nthreads, double* par_out, double* cov_out, double* chi2_out,
+             int update_2d, int round32, int nthreads, double* par_out, double* cov_out, double* chi2_out,
              int32_t* nused_out, uint32_t* status_out,
              double* lay_par, double* lay_cov, double* lay_chi2) {
-    FitArgs a{par, cov, q, offsets, stype, sval, hits, hitcov, bz, chi2_cut, form, update_2d,
+    FitArgs a{par, cov, q, offsets, stype, sval, hits, hitcov, bz, chi2_cut, form, update_2d, round32,
               par_out, cov_out, chi2_out, nused_out, status_out, lay_par, lay_cov, lay_chi2};
     int nt = nthreads > 0 ? nthreads : (int)std::max(1u, std::thread::hardware_concurrency());
     if (nt > n) nt = (int)std::max<int64_t>(1, n);

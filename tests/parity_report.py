@@ -2,8 +2,8 @@
 workloads fitted on the GPU and by the FP64 oracle, compared element by
 element.  Prints, per workload, the largest error of every output, how many
 covariance elements pass under each branch of the rule in tests/parity.py,
-and the distribution of the final-crossing conditioning 1/cos(incidence)
-over the elements that need it.
+how many tracks had a bound widened by the oracle's measured FP32
+sensitivity, and how many end at a shallow incidence.
 
 Needs a GPU and the built libraries:  python -m tests.parity_report [--dump DIR]
 (--dump writes the GPU and oracle outputs of the tracks that fail a check
@@ -57,39 +57,38 @@ def _gpu_ragged(p2r, ctx, d, cut):
 
 
 def report(name, g, r, final_surface, dump=None):
-    from tests.parity import NORM_TOL, compare, covariance_breakdown, failures
-    f = failures(g, r, final_surface)
+    from tests.parity import NORM_TOL, compare, failures, incidence_condition
+    f = failures(g, r)
     n = len(g["chi2"])
     print(f"== {name}: {n} tracks, {len(f['excluded'])} excluded", flush=True)
     bad = {k: f[k] for k in ("status", "par", "chi2", "cov")}
     print("  tracks failing: " + ", ".join(f"{k} {len(v)}" for k, v in bad.items()))
     for k in ("par", "chi2", "cov"):
-        rr = f[k + "_ratio"]
-        print(f"  {k}: largest error / tolerance {rr.max():.3f}; 99.99% {np.quantile(rr, 0.9999):.3f}; "
-              f"99.9% {np.quantile(rr, 0.999):.3f}")
+        rr, raw, w = f[k + "_ratio"], f[k + "_raw"], f["widen_" + k]
+        print(f"  {k}: largest error / bound {rr.max():.3f}; 99.99% {np.quantile(rr, 0.9999):.3f}; "
+              f"99.9% {np.quantile(rr, 0.999):.3f}; error / base bound above 1 in {int((raw > 1).sum())} tracks; "
+              f"bound widened in {int((w > 1).sum())} tracks (widest x{w.max():.3g})")
     if dump is not None:
         idx = np.unique(np.concatenate([v for v in bad.values()] + [np.zeros(0, np.int64)])).astype(np.int64)
+        extra = {}
+        if "f32" in r:
+            extra = {f"s_{k}": np.asarray(r["f32"][k])[idx] for k in ("par", "cov", "chi2", "status")}
         np.savez(dump, idx=idx, **{f"g_{k}": np.asarray(g[k])[idx] for k in ("par", "cov", "chi2", "status")},
-                 **{f"r_{k}": np.asarray(r[k])[idx] for k in ("par", "cov", "chi2", "status", "nused")})
+                 **{f"r_{k}": np.asarray(r[k])[idx] for k in ("par", "cov", "chi2", "status", "nused")}, **extra)
     if any(len(v) for v in bad.values()):
         return None
     rep = compare(g, r, ctx=name, final_surface=final_surface)
-    br = covariance_breakdown(g, r, final_surface)
     print("  max rel error, parameters (x y z 1/pT phi theta):",
           " ".join(f"{v:.2e}" for v in rep["max_rel_par"]))
     print(f"  max rel error, chi2: {rep['max_rel_chi2']:.2e}")
     print(f"  covariance, error / sqrt(C_ii C_jj): max {rep['cov_norm_err_max']:.2e}, "
           f"99.9% {rep['cov_norm_err_p999']:.2e} (bound {NORM_TOL:g})")
     print(f"  covariance elements: {rep['cov_rel_pass']} pass the relative bound, "
-          f"{rep['cov_norm_only']} only the normalised one, {rep['cov_kappa_only']} only with the "
-          f"conditioning factor; {rep['fp64_fallbacks']} tracks took the FP64 update")
-    print(f"  tracks ending on a cylinder with 1/cos(incidence) above 2, 5, 10, 20, 50: "
-          + ", ".join(str(c) for c in br["kappa_counts"]))
-    if br["needs_kappa"]:
-        print(f"  elements that need the factor: {br['needs_kappa']} in {br['tracks_kappa']} tracks; "
-              f"per packed index {br['per_index']}")
-        print(f"  required factor / track's 1/cos(incidence): max {br['ratio_max']:.3f}; "
-              f"their 1/cos(incidence): min {br['kappa_min']:.1f}, max {br['kappa_max']:.1f}")
+          f"{rep['cov_norm_only']} only the normalised one, {rep['cov_widened_only']} only the widened one; "
+          f"{rep['tracks_widened']} tracks had a bound widened; {rep['fp64_fallbacks']} tracks took the FP64 update")
+    kap = incidence_condition(r["par"], final_surface)
+    print("  tracks whose final surface has 1/cos(incidence) above 2, 5, 10, 20, 50: "
+          + ", ".join(str(int((kap > t).sum())) for t in (2, 5, 10, 20, 50)))
     return rep
 
 

@@ -89,7 +89,7 @@ def _table(name, e32, e64):
     print("\n".join(lines), flush=True)
 
 
-@pytest.mark.parametrize("W", [64, 256])
+@pytest.mark.parametrize("W", [32, 64, 128, 256])
 def test_fp64_p2r_matches_oracle_tightly(ctx, W):
     d = ev.make_barrel_event(ev.P2R_THROUGHPUT.with_(seed=71), n_tracks=6000)
     r = oracle.fit_event(d, "barrel")

@@ -148,7 +148,7 @@ def _fit(ctx, d, mlp=None, W=64):
                 status=st.cpu().numpy().view(np.uint32)), int(ev_.item())
 
 
-@pytest.mark.parametrize("W", [64, 128])
+@pytest.mark.parametrize("W", [32, 64, 128, 256])
 def test_learned_fit_matches_oracle(ctx, trained, W):
     d = ev.make_barrel_event(ev.LEARNED_EVAL, n_tracks=4099)
     r = oracle.fit_event(d, "barrel")

@@ -1,12 +1,16 @@
 """Transfer-inclusive host pipeline (chunks on three streams) against the
-device-resident fit: the same kernels on the same data, so the results are
-bit-for-bit identical whatever the chunking."""
+FP64 oracle, and against the device-resident fit: the same kernels on the
+same data, so those results are bit-for-bit identical whatever the
+chunking."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2401_14221_amd as p2r
 from synth import events as ev
+
+from .parity import compare
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +69,12 @@ def test_host_pipeline_equals_device_fit(ctx, which, W, n, chunk):
     assert torch.equal(a[1], b[1])
     assert torch.equal(a[2], b[2])
     assert b[0].shape[0] == nb
+    # and the pipeline's results against the oracle
+    g = dict(par=pb.numpy(), cov=cb.numpy(), chi2=b[1].numpy(), status=b[2].numpy().view(np.uint32))
+    r = oracle.fit_event(d, "barrel" if which == 0 else "disk")
+    print(f"pipeline which={which} W={W} n={n}",
+          compare(g, r, ctx=f"host pipeline which={which}", final_surface="cylinder" if which == 0 else "plane"),
+          flush=True)
 
 
 def test_host_pipeline_edge_cases(ctx):
