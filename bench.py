@@ -436,27 +436,54 @@ def learned_leg(ctx, args, stream, ev, p2r, dev):
     return res
 
 
-def cpu_baseline(d, ev):
-    """FP64 oracle on the same workload, all host cores (at most 16 threads).
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    The whole 960,000-track workload is fitted: about 1.2 s per run on 16
-    threads (~20 s of CPU-thread work), one warm-up and three timed runs."""
-    import oracle
-    ncores = len(os.sched_getaffinity(0))
-    nthreads = min(ncores, 16)
-    n = d["par"].shape[0]
-    oracle.fit_event(d, "barrel", nthreads=nthreads)          # warm-up
+
+def _time_oracle(oracle, d, nthreads, warmup=2, runs=10):
+    for _ in range(warmup):
+        oracle.fit_event(d, "barrel", nthreads=nthreads, sensitivity=False)
     times = []
-    for _ in range(3):
+    for _ in range(runs):
         t = time.perf_counter()
-        oracle.fit_event(d, "barrel", nthreads=nthreads)
+        oracle.fit_event(d, "barrel", nthreads=nthreads, sensitivity=False)
         times.append(time.perf_counter() - t)
-    tl = n * d["hits"].shape[1]
-    v = tl / float(np.mean(times))
-    log(f"cpu oracle: {v:.3e} track-layers/s on {nthreads} threads ({np.mean(times):.2f} s per run)")
+    return float(np.mean(times)), float(np.std(times))
+
+
+def cpu_baseline(d, ev):
+    """FP64 oracle timed on the host: all cores of this process's CPU set (at
+    most 16 threads) on the whole workload, and one core on the first 1/16 of
+    its tracks; 2 warm-ups, then the mean of 10 runs, each.
+
+    About 1.2 s per all-core run and 1.2 s per single-core run on 16-core
+    hosts (~30 s in total)."""
+    import oracle
+    host_cpus = len(os.sched_getaffinity(0))
+    nthreads = min(host_cpus, 16)
+    n, L = d["par"].shape[0], d["hits"].shape[1]
+    m, s = _time_oracle(oracle, d, nthreads)
+    v = n * L / m
+    n1 = max(1, n // 16)
+    d1 = {k: (v_[:n1] if k in ("par", "cov", "q", "hits", "hitcov") else v_) for k, v_ in d.items()}
+    m1, s1 = _time_oracle(oracle, d1, 1)
+    v1 = n1 * L / m1
+    model = _cpu_model()
+    log(f"cpu oracle ({model}): {v:.3e} track-layers/s on {nthreads} threads ({m:.2f} +- {s:.2f} s per run); "
+        f"{v1:.3e} on 1 thread ({m1:.2f} +- {s1:.2f} s per run of {n1} tracks)")
     return {"value": v, "unit": UNIT, "cores": nthreads, "kind": "oracle",
-            "sample": f"the whole workload, {n} tracks x {d['hits'].shape[1]} layers, FP64 oracle "
-                      f"(dual-number Jacobian, full 6x6 algebra), mean of 3 runs after 1 warm-up"}
+            "cpu_model": model, "host_cpus": host_cpus,
+            "single_core": {"value": v1, "unit": UNIT, "cores": 1,
+                            "sample": f"the first {n1} tracks x {L} layers"},
+            "sample": f"the whole workload, {n} tracks x {L} layers, FP64 oracle (dual-number Jacobian, "
+                      f"full 6x6 algebra), mean of 10 runs after 2 warm-ups (s.d. {s:.3f} s)"}
 
 
 if __name__ == "__main__":
