@@ -173,8 +173,16 @@ int p2z_propagate_update(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, i
  * works but serialises them.  The pipeline is ordered after the work already
  * queued on `stream`, and `stream` waits for its end; the call returns
  * without waiting, and the host buffers must stay untouched until `stream`
- * reaches that point.  Staging buffers (three chunks) live in the context:
- * calls on one context must not overlap.  Not with an MLP. */
+ * reaches that point.  Staging buffers (three chunks) live in the context,
+ * sized by p2r_ctx_reserve_host: a call whose chunks or layer count exceed
+ * the reservation returns P2R_ENOSPACE without copying or launching
+ * anything.  Calls on one context must not overlap.  Not with an MLP. */
+/* Sizes the host pipeline's staging (three streams, each one chunk of
+ * chunk_tracks tracks, 0 = 131072, rounded up to 256, with max_layers
+ * layers, up to 4096) and creates its streams and events.  Grows only;
+ * waits for the pipeline's previous work before it reallocates.  The only
+ * call that allocates for the pipeline. */
+int p2r_ctx_reserve_host(p2r_ctx* ctx, int32_t max_layers, int32_t chunk_tracks);
 int p2r_propagate_update_host(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, int32_t n_layers,
                               const float* layer_r, const float* trk_in, const float* hits, float* trk_out,
                               float* chi2_out, uint32_t* status, int32_t chunk_tracks, void* stream);
@@ -271,7 +279,11 @@ const char* p2r_variant_at(int which, int i);
  * Pass the handle as p2r_opts.mlp to p2r_propagate_update for the learned
  * start.  Buffers are device pointers unless stated. */
 typedef struct p2r_mlp p2r_mlp;
-int p2r_mlp_create(p2r_ctx* ctx, p2r_mlp** out);        /* allocates master weights, Adam state */
+/* Allocates the FP32 master weights, Adam state and BF16 copy, and
+ * initialises the weights from `seed` (W1, W2 uniform in +-sqrt(6 / fan_in),
+ * w3 the same scaled by 0.1, biases 0; a counter-based hash of the seed and
+ * the parameter index); synchronises. */
+int p2r_mlp_create(p2r_ctx* ctx, uint64_t seed, p2r_mlp** out);
 void p2r_mlp_destroy(p2r_mlp* mlp);
 int p2r_mlp_n_params(void);
 /* host_params: host array of p2r_mlp_n_params() floats; resets Adam; synchronises. */
@@ -282,12 +294,17 @@ int p2r_mlp_get_params(p2r_mlp* mlp, float* host_params);
 int p2r_mlp_features(p2r_mlp* mlp, const p2r_opts* opts, int32_t n, const float* par, const float* q,
                      const float* R, const float* s_label, float* x, float* t, float* s_line, void* stream);
 int p2r_mlp_forward(p2r_mlp* mlp, const float* x, float* y, int32_t B, void* stream);
+/* Sizes the per-workgroup gradient partials for batches of up to max_batch
+ * (grows only; waits for the device before it reallocates).  The only MLP
+ * call besides p2r_mlp_create that allocates. */
+int p2r_mlp_reserve(p2r_mlp* mlp, int32_t max_batch);
 /* Gradients of the mean squared error over the batch (grads_out [n_params], loss_out [1]; nullable).
- * Deterministic (per-workgroup partials summed in a fixed order); the partial
- * buffer is allocated on the first call and grown when B grows. */
+ * Deterministic (per-workgroup partials summed in a fixed order).  B must be
+ * within p2r_mlp_reserve's max_batch, else P2R_ENOSPACE and nothing runs. */
 int p2r_mlp_grads(p2r_mlp* mlp, const float* x, const float* t, int32_t B, float* grads_out,
                   float* loss_out, void* stream);
-/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights, then a fresh BF16 copy. */
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights, then a fresh BF16 copy
+ * (same batch limit as p2r_mlp_grads). */
 int p2r_mlp_train_step(p2r_mlp* mlp, const float* x, const float* t, int32_t B, float lr,
                        float* loss_out, void* stream);
 /* Checkpoint (host file): step, FP32 weights and Adam moments; load restores them bit for bit. */

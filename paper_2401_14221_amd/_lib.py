@@ -86,7 +86,9 @@ def library():
         L.fit_tracks_batched_noalloc.argtypes = [vp, C.POINTER(Opts), i32, i64, i32] + [vp] * 13
         L.p2r_ctx_reserve.argtypes = [vp, i32, i32]
         L.p2r_device_allocations.restype = C.c_ulonglong
-        L.p2r_mlp_create.argtypes = [vp, C.POINTER(vp)]
+        L.p2r_ctx_reserve_host.argtypes = [vp, i32, i32]
+        L.p2r_mlp_create.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+        L.p2r_mlp_reserve.argtypes = [vp, i32]
         L.p2r_mlp_destroy.argtypes = [vp]
         L.p2r_mlp_destroy.restype = None
         L.p2r_mlp_n_params.restype = C.c_int
@@ -193,6 +195,10 @@ class Context:
         _check(library().p2r_ctx_reserve(self._h, int(max_tracks), int(max_surfaces)))
         self._ragged_cap = (max(self._ragged_cap[0], int(max_tracks)), max(self._ragged_cap[1], int(max_surfaces)))
 
+    def reserve_host(self, max_layers: int, chunk_tracks: int = 0):
+        """Size the host pipeline's staging (p2r_ctx_reserve_host); grow-only."""
+        _check(library().p2r_ctx_reserve_host(self._h, int(max_layers), int(chunk_tracks)))
+
     # --------------------------------------------------------------- fits
     def _outputs(self, trk_in, n):
         dev = trk_in.device
@@ -231,6 +237,9 @@ class Context:
             out = (torch.empty_like(trk_in).pin_memory(), torch.empty(n_tracks, dtype=torch.float32).pin_memory(),
                    torch.empty(n_tracks, dtype=torch.int32).pin_memory())
         trk_out, chi2, status = out
+        if chunk_tracks >= 0 and 0 <= layer.numel() <= 4096:
+            # sizing happens here, before the C call, which itself never allocates
+            self.reserve_host(layer.numel(), chunk_tracks)
         fn = library().p2r_propagate_update_host if which == 0 else library().p2z_propagate_update_host
         _check(fn(self._h, C.byref(opts), n_tracks, layer.numel(), _ptr(layer), _ptr(trk_in), _ptr(hits),
                   _ptr(trk_out), _ptr(chi2), _ptr(status), int(chunk_tracks), _stream(stream)))
@@ -277,10 +286,11 @@ class Context:
 class Mlp:
     """Path-length MLP on the GPU (weights, Adam state and kernels in libp2r)."""
 
-    def __init__(self, ctx: Context, params=None):
+    def __init__(self, ctx: Context, params=None, seed: int = 0):
         self.ctx = ctx
         self._h = vp()
-        _check(library().p2r_mlp_create(ctx._h, C.byref(self._h)))
+        self._batch_cap = 0
+        _check(library().p2r_mlp_create(ctx._h, int(seed) & (2**64 - 1), C.byref(self._h)))
         self.n_params = library().p2r_mlp_n_params()
         if params is not None:
             self.set_params(params)
@@ -329,13 +339,25 @@ class Mlp:
         _check(library().p2r_mlp_forward(self._h, _ptr(x), _ptr(y), x.shape[0], _stream(stream)))
         return y
 
+    def reserve(self, max_batch: int):
+        """Size the gradient partials (p2r_mlp_reserve); grow-only."""
+        _check(library().p2r_mlp_reserve(self._h, int(max_batch)))
+        self._batch_cap = max(self._batch_cap, int(max_batch))
+
+    def _ensure(self, B: int):
+        # sizing happens here, before the C call, which itself never allocates
+        if 0 < B and B > self._batch_cap:
+            self.reserve(B)
+
     def grads(self, x, t, stream=None):
+        self._ensure(x.shape[0])
         g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
         _check(library().p2r_mlp_grads(self._h, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss), _stream(stream)))
         return g, loss
 
     def train_step(self, x, t, lr, loss_out=None, stream=None):
+        self._ensure(x.shape[0])
         _check(library().p2r_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], float(lr), _ptr(loss_out),
                                             _stream(stream)))
 

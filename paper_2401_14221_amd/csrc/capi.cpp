@@ -151,7 +151,7 @@ struct p2r_ctx {
     RaggedKey key;
     bool have_graph = false;
     // host pipeline (p2r/p2z_propagate_update_host): streams, events and
-    // per-stream staging buffers, created on first use and grown when needed
+    // per-stream staging buffers, created and grown by p2r_ctx_reserve_host
     static constexpr int NPIPE = 3;
     hipStream_t pipe_s[NPIPE] = {};
     hipEvent_t pipe_done[NPIPE] = {};
@@ -453,6 +453,57 @@ int p2z_propagate_update(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tracks, i
                             stream);
 }
 
+// staging of one pipeline stream for chunks of `tracks` (a whole number of
+// layout blocks) and n_layers layers: tracks in and out [28][tracks], hits
+// [n_layers][9][tracks], chi2 and status [tracks]
+static size_t pipe_stage_bytes(int64_t tracks, int32_t n_layers) {
+    return sizeof(float) * (size_t)tracks * (2 * 28 + (size_t)n_layers * 9 + 2);
+}
+static constexpr int32_t PIPE_DEFAULT_CHUNK = 131072;
+
+int p2r_ctx_reserve_host(p2r_ctx* ctx, int32_t max_layers, int32_t chunk_tracks) {
+    if (!ctx) return fail(P2R_EINVAL, "ctx is NULL");
+    if (max_layers < 0 || max_layers > 4096) return fail(P2R_EINVAL, "max_layers %d outside 0..4096", max_layers);
+    if (chunk_tracks < 0) return fail(P2R_EINVAL, "chunk_tracks must be >= 0");
+    // any layout width (64, 128 or 256) rounds a chunk up to at most this
+    const int64_t tracks = ((int64_t)(chunk_tracks > 0 ? chunk_tracks : PIPE_DEFAULT_CHUNK) + 255) / 256 * 256;
+    const size_t bytes = pipe_stage_bytes(tracks, max_layers);
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e;
+    if (!ctx->pipe_start) {
+        for (int k = 0; k < p2r_ctx::NPIPE; ++k) {
+            if ((e = hipStreamCreateWithFlags(&ctx->pipe_s[k], hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreateWithFlags");
+            if ((e = hipEventCreateWithFlags(&ctx->pipe_done[k], hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "hipEventCreateWithFlags");
+        }
+        if ((e = hipEventCreateWithFlags(&ctx->pipe_start, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    if (bytes > ctx->pipe_bytes) {
+        for (int k = 0; k < p2r_ctx::NPIPE; ++k) {
+            (void)hipStreamSynchronize(ctx->pipe_s[k]);
+            if (ctx->pipe_buf[k]) (void)hipFree(ctx->pipe_buf[k]);
+            ctx->pipe_buf[k] = nullptr;
+        }
+        ctx->pipe_bytes = 0;
+        for (int k = 0; k < p2r_ctx::NPIPE; ++k)
+            if ((e = dev_alloc(&ctx->pipe_buf[k], bytes)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        ctx->pipe_bytes = bytes;
+    }
+    if (max_layers > ctx->pipe_surf_cap) {
+        for (int k = 0; k < p2r_ctx::NPIPE; ++k) (void)hipStreamSynchronize(ctx->pipe_s[k]);
+        if (ctx->pipe_surf) (void)hipFree(ctx->pipe_surf);
+        ctx->pipe_surf = nullptr;
+        ctx->pipe_surf_cap = 0;
+        if ((e = dev_alloc(&ctx->pipe_surf, sizeof(float) * (max_layers > 0 ? max_layers : 1))) != hipSuccess)
+            return hip_fail(e, "hipMalloc");
+        ctx->pipe_surf_cap = max_layers;
+    }
+    return P2R_OK;
+}
+
 // Host-to-host fit in chunks on NPIPE streams: chunk c is copied in, fitted
 // and copied back on stream c % NPIPE, into that stream's staging buffers,
 // so the copies of one chunk overlap the fit of another; stream order makes
@@ -478,44 +529,17 @@ static int propagate_host(int which, p2r_ctx* ctx, const p2r_opts* opts, int32_t
     if (rc) return rc;
     const int W = v->width;
     const int64_t nb = ((int64_t)n_tracks + W - 1) / W;
-    int64_t cb = chunk_tracks > 0 ? ((int64_t)chunk_tracks + W - 1) / W : (131072 + W - 1) / W;   // blocks per chunk
+    int64_t cb = ((int64_t)(chunk_tracks > 0 ? chunk_tracks : PIPE_DEFAULT_CHUNK) + W - 1) / W;   // blocks per chunk
     if (cb > nb) cb = nb;
+    const size_t trk_f = (size_t)cb * 28 * W, hit_f = (size_t)cb * n_layers * 9 * W, trk_n = (size_t)cb * W;
+    const size_t bytes = pipe_stage_bytes(cb * W, n_layers);   // = 4 (2 trk_f + hit_f + 2 trk_n)
+    if (!ctx->pipe_start || bytes > ctx->pipe_bytes || n_layers > ctx->pipe_surf_cap)
+        return fail(P2R_ENOSPACE, "host pipeline staging for %lld tracks per chunk and %d layers is not reserved "
+                    "(p2r_ctx_reserve_host)", (long long)(cb * W), n_layers);
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e;
-    if (!ctx->pipe_start) {
-        for (int k = 0; k < p2r_ctx::NPIPE; ++k) {
-            if ((e = hipStreamCreateWithFlags(&ctx->pipe_s[k], hipStreamNonBlocking)) != hipSuccess)
-                return hip_fail(e, "hipStreamCreateWithFlags");
-            if ((e = hipEventCreateWithFlags(&ctx->pipe_done[k], hipEventDisableTiming)) != hipSuccess)
-                return hip_fail(e, "hipEventCreateWithFlags");
-        }
-        if ((e = hipEventCreateWithFlags(&ctx->pipe_start, hipEventDisableTiming)) != hipSuccess)
-            return hip_fail(e, "hipEventCreateWithFlags");
-    }
-    // staging per stream: tracks in and out [cb][28][W], hits [cb][L][9][W]
-    // (p2z: [L][cb][9][64]), chi2 and status [cb W]
-    const size_t trk_f = (size_t)cb * 28 * W, hit_f = (size_t)cb * n_layers * 9 * W, trk_n = (size_t)cb * W;
-    const size_t bytes = sizeof(float) * (2 * trk_f + hit_f + 2 * trk_n);
     hipStream_t us = (hipStream_t)stream;
-    if (bytes > ctx->pipe_bytes) {
-        for (int k = 0; k < p2r_ctx::NPIPE; ++k) {
-            (void)hipStreamSynchronize(ctx->pipe_s[k]);
-            if (ctx->pipe_buf[k]) (void)hipFree(ctx->pipe_buf[k]);
-            ctx->pipe_buf[k] = nullptr;
-        }
-        ctx->pipe_bytes = 0;
-        for (int k = 0; k < p2r_ctx::NPIPE; ++k)
-            if ((e = dev_alloc(&ctx->pipe_buf[k], bytes)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        ctx->pipe_bytes = bytes;
-    }
-    if (n_layers > ctx->pipe_surf_cap) {
-        if (ctx->pipe_surf) (void)hipFree(ctx->pipe_surf);
-        ctx->pipe_surf = nullptr;
-        ctx->pipe_surf_cap = 0;
-        if ((e = dev_alloc(&ctx->pipe_surf, sizeof(float) * n_layers)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        ctx->pipe_surf_cap = n_layers;
-    }
     // the surface table, then the pipeline, after the caller's queued work
     if (n_layers > 0 &&
         (e = hipMemcpyAsync(ctx->pipe_surf, surf, sizeof(float) * n_layers, hipMemcpyHostToDevice, us)) != hipSuccess)
@@ -801,7 +825,25 @@ int fit_tracks_batched_noalloc(p2r_ctx* ctx, const p2r_opts* opts, int32_t n_tra
 
 static int mlp_check(p2r_mlp* m) { return m ? P2R_OK : fail(P2R_EINVAL, "mlp is NULL"); }
 
-int p2r_mlp_create(p2r_ctx* ctx, p2r_mlp** out) {
+// Initial weights from a seed: W1, W2 uniform in +-sqrt(6 / fan_in), w3 the
+// same times 0.1, biases 0; element k of the flat vector draws
+// hash_u01(seed-derived key, k).
+static void mlp_init_params(uint64_t seed, std::vector<float>& w) {
+    w.assign(p2r::MLP_NPARAM, 0.0f);
+    const uint32_t key = (uint32_t)(seed ^ (seed >> 32)) * 0x9E3779B1u + 0x6D4C5031u;
+    const int nin = 7, nh = 64;
+    auto fill = [&](size_t off, size_t count, int fan_in, float scale) {
+        const float lim = std::sqrt(6.0f / (float)fan_in) * scale;
+        for (size_t k = 0; k < count; ++k)
+            w[off + k] = (2.0f * p2r::hash_u01(key, (uint32_t)(off + k)) - 1.0f) * lim;
+    };
+    size_t o = 0;
+    fill(o, (size_t)nh * nin, nin, 1.0f);  o += (size_t)nh * nin + nh;        // W1, b1 = 0
+    fill(o, (size_t)nh * nh, nh, 1.0f);    o += (size_t)nh * nh + nh;         // W2, b2 = 0
+    fill(o, (size_t)nh, nh, 0.1f);                                            // w3, b3 = 0
+}
+
+int p2r_mlp_create(p2r_ctx* ctx, uint64_t seed, p2r_mlp** out) {
     if (!ctx || !out) return fail(P2R_EINVAL, "NULL argument");
     *out = nullptr;
     DeviceGuard g(ctx->device);
@@ -823,6 +865,13 @@ int p2r_mlp_create(p2r_ctx* ctx, p2r_mlp** out) {
     uintptr_t wp = (reinterpret_cast<uintptr_t>(f + 4 * np + 64) + 255) & ~uintptr_t(255);
     m->d.w = reinterpret_cast<p2r::MlpWeights*>(wp);
     m->d.step = 0;
+    std::vector<float> w;
+    mlp_init_params(seed, w);
+    if ((e = hipMemcpy(m->d.master, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = p2r::mlp_recast(m->d, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+        (void)hipFree(m->block);
+        return hip_fail(e, "p2r_mlp_create (initial weights)");
+    }
     *out = m.release();
     return P2R_OK;
 }
@@ -835,10 +884,16 @@ void p2r_mlp_destroy(p2r_mlp* m) {
     delete m;
 }
 
-// per-workgroup gradient rows for a batch of B (grown on demand)
-static int mlp_reserve(p2r_mlp* m, int32_t B) {
+// per-workgroup gradient rows for batches up to B
+int p2r_mlp_reserve(p2r_mlp* m, int32_t B) {
+    int rc = mlp_check(m);
+    if (rc) return rc;
+    if (B <= 0) return fail(P2R_EINVAL, "batch must be positive");
     const int nb = p2r::mlp_grad_blocks(B);
     if (nb <= m->d.part_blocks) return P2R_OK;
+    DeviceGuard g(m->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    (void)hipDeviceSynchronize();          // earlier gradient calls may still read the old rows
     if (m->d.part) (void)hipFree(m->d.part);
     m->d.part = nullptr;
     m->d.part_blocks = 0;
@@ -903,9 +958,9 @@ int p2r_mlp_grads(p2r_mlp* m, const float* x, const float* t, int32_t B, float* 
     if (rc) return rc;
     if (B <= 0) return fail(P2R_EINVAL, "batch must be positive");
     if (!x || !t) return fail(P2R_EINVAL, "NULL buffer");
+    if (p2r::mlp_grad_blocks(B) > m->d.part_blocks)
+        return fail(P2R_ENOSPACE, "gradient partials for a batch of %d are not reserved (p2r_mlp_reserve)", B);
     DeviceGuard g(m->device);
-    rc = mlp_reserve(m, B);
-    if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = p2r::mlp_grads(m->d, x, t, B, s);
     if (e == hipSuccess && grads_out)
@@ -916,9 +971,9 @@ int p2r_mlp_grads(p2r_mlp* m, const float* x, const float* t, int32_t B, float* 
 
 int p2r_mlp_train_step(p2r_mlp* m, const float* x, const float* t, int32_t B, float lr, float* loss_out,
                        void* stream) {
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(P2R_EINVAL, "lr must be > 0");
     int rc = p2r_mlp_grads(m, x, t, B, nullptr, loss_out, stream);
     if (rc) return rc;
-    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(P2R_EINVAL, "lr must be > 0");
     DeviceGuard g(m->device);
     m->d.step += 1;
     hipError_t e = p2r::mlp_adam(m->d, lr, m->d.step, (hipStream_t)stream);

@@ -2,6 +2,8 @@
 FP64 oracle, and against the device-resident fit: the same kernels on the
 same data, so those results are bit-for-bit identical whatever the
 chunking."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -96,3 +98,38 @@ def test_host_pipeline_edge_cases(ctx):
     torch.cuda.synchronize()
     a = _device(ctx, 1, d, 64)
     assert torch.equal(a[1], r[1])
+
+
+def test_host_pipeline_no_allocation_after_reserve(ctx):
+    """The pipeline calls allocate nothing once p2r_ctx_reserve_host has sized
+    the staging; more layers or larger chunks than reserved are refused
+    before anything is copied or launched."""
+    c = p2r.Context(0)
+    try:
+        d = ev.make_disk_event(ev.P2Z_THROUGHPUT.with_(seed=84), n_tracks=3000)
+        trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], 64).pin_memory()
+        hits = p2r.pack_hits_p2z(d["hits"], d["hitcov"]).pin_memory()
+        surf = torch.as_tensor(d["surf"], dtype=torch.float32)
+        L = surf.numel()
+        c.reserve_host(L, 1024)
+        torch.cuda.synchronize()
+        n0 = p2r.device_allocations()
+        s = torch.cuda.Stream()
+        r1 = c.propagate_update_host(1, 3000, surf, trk, hits, chunk_tracks=1024, stream=s)
+        s.synchronize()
+        r2 = c.propagate_update_host(1, 3000, surf, trk, hits, chunk_tracks=512, stream=s)
+        s.synchronize()
+        assert p2r.device_allocations() == n0
+        assert torch.equal(r1[1], r2[1]) and torch.equal(r1[2], r2[2])
+        # the raw C call (no binding-side sizing) with chunks above the reservation
+        lib = p2r._lib.library()
+        o = p2r._lib.default_opts()
+        out = [torch.empty_like(trk).pin_memory(), torch.empty(3000).pin_memory(),
+               torch.empty(3000, dtype=torch.int32).pin_memory()]
+        rc = lib.p2z_propagate_update_host(c._h, ctypes.byref(o), 3000, L, surf.data_ptr(), trk.data_ptr(),
+                                           hits.data_ptr(), out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                                           2048, None)
+        assert rc == p2r.P2R_ENOSPACE
+        assert p2r.device_allocations() == n0
+    finally:
+        c.close()
