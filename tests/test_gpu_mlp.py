@@ -66,6 +66,25 @@ def test_forward_matches_bf16_reference(ctx, B):
     assert err < 1e-4
 
 
+def _grad_term_bounds(p, x, t):
+    """Per gradient element, the sum and the largest of |per-sample term| (the
+    condition of each batch sum), from the BF16-operand reference's
+    intermediates."""
+    y, c = omlp.forward(p, x, bf16=True)
+    B = y.shape[0]
+    W2, W3 = np.asarray(p["W2"], np.float64), np.asarray(p["W3"], np.float64)
+    dy = np.abs(2.0 * (y - t) / B)
+    dz2 = dy[:, None] * np.abs(W3[0])[None, :] * (c["z2"] > 0)
+    dz1 = (np.abs(omlp.bf16_round(dz2)) @ np.abs(omlp.bf16_round(W2))) * (c["z1"] > 0)
+    h1, h2, xx = np.abs(c["h1"]), np.abs(c["h2"]), np.abs(c["x"])
+    S = dict(W3=(dy @ h2)[None, :], b3=np.array([dy.sum()]), W2=dz2.T @ h1, b2=dz2.sum(0),
+             W1=dz1.T @ xx, b1=dz1.sum(0))
+    M = dict(W3=(dy[:, None] * h2).max(0)[None, :], b3=np.array([dy.max()]),
+             W2=(dz2[:, :, None] * h1[:, None, :]).max(0), b2=dz2.max(0),
+             W1=(dz1[:, :, None] * xx[:, None, :]).max(0), b1=dz1.max(0))
+    return S, M
+
+
 def test_grads_match_bf16_reference(ctx):
     d, x, _ = _pairs()
     B = 2048
@@ -78,12 +97,18 @@ def test_grads_match_bf16_reference(ctx):
     g = learned.split_params(g.cpu().numpy())
     l_ref, g_ref = omlp.loss_and_grads(p, x, t, bf16=True)
     assert float(loss.item()) == pytest.approx(l_ref, rel=1e-4)
+    S, M = _grad_term_bounds(p, x, t)
     for k in g_ref:
-        a, b = g[k].reshape(-1).astype(np.float64), g_ref[k].reshape(-1)
-        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        cos = a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
-        print(f"grad {k}: rel L2 {rel:.2e}, cosine {cos:.8f}", flush=True)
-        assert rel < 1e-3 and cos > 0.9999, k
+        a, b = g[k].astype(np.float64), g_ref[k]
+        # element-wise: FP32 accumulation over the batch, |err| <= ~B eps32 sum_b |term_b|
+        # (1e-5 covers B = 2048 summed in blocks), plus the rare BF16 operand that an FP32
+        # intermediate rounds the other way (h1 or dz2 of one sample: at most 2^-8 of that
+        # sample's term, allowed three times)
+        bound = 1e-5 * S[k] + 3 * 2.0 ** -8 * M[k] + 1e-30
+        r = np.abs(a - b) / bound
+        print(f"grad {k}: max |err| / bound {r.max():.3f}; rel L2 "
+              f"{np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30):.2e}", flush=True)
+        assert (r <= 1.0).all(), (k, np.unravel_index(np.argmax(r), r.shape), r.max())
 
 
 def test_adam_step_and_checkpoint(ctx, tmp_path):
@@ -110,6 +135,59 @@ def test_adam_step_and_checkpoint(ctx, tmp_path):
     for _ in range(2):
         m2.train_step(x, t, 1e-3)
     assert np.array_equal(m2.get_params(), a)
+
+
+def test_create_seed_initialises_weights(ctx):
+    """p2r_mlp_create's seed: reproducible, seed-dependent, fan-in-scaled
+    uniform weights and zero biases."""
+    a = learned.split_params(p2r.Mlp(ctx, seed=5).get_params())
+    b = learned.split_params(p2r.Mlp(ctx, seed=5).get_params())
+    c = learned.split_params(p2r.Mlp(ctx, seed=6).get_params())
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    for k, fan, scale in (("W1", 7, 1.0), ("W2", 64, 1.0), ("W3", 64, 0.1)):
+        lim = np.sqrt(6.0 / fan) * scale
+        w = a[k].astype(np.float64)
+        assert np.abs(w).max() <= lim and not np.array_equal(a[k], c[k]), k
+        assert abs(w.mean()) < 0.1 * lim, k
+        assert w.std() == pytest.approx(lim / np.sqrt(3), rel=0.2), k
+    for k in ("b1", "b2", "b3"):
+        assert not a[k].any(), k
+
+
+def test_training_from_seed_reduces_loss(ctx):
+    """A short training run from a fixed seed, always (not the committed
+    network): the loss falls and the proposal beats the straight line."""
+    m, hist = learned.train(ctx, n_tracks=40_000, epochs=4, batch=4096, seed=1234)
+    print("loss per epoch", " ".join(f"{h:.4e}" for h in hist), flush=True)
+    assert all(np.isfinite(hist)) and hist[-1] < 0.5 * hist[0]
+    q = learned.proposal_quality(m, n_tracks=5000, seed=98)
+    print("proposal quality after the short run", q, flush=True)
+    assert q["median_err_mlp"] < q["median_err_line"]
+
+
+def test_no_device_allocation_after_reserve(ctx):
+    """Gradient and training calls allocate nothing once p2r_mlp_reserve has
+    sized the batch; a larger batch is refused before anything runs."""
+    d, x, _ = _pairs()
+    m = p2r.Mlp(ctx, seed=3)
+    m.reserve(512)
+    xt = torch.as_tensor(x[:512], dtype=torch.float32, device="cuda")
+    tt = torch.zeros(512, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    n0 = p2r.device_allocations()
+    for B in (512, 100, 512):
+        m.grads(xt[:B], tt[:B])
+        m.train_step(xt[:B], tt[:B], 1e-3)
+    torch.cuda.synchronize()
+    assert p2r.device_allocations() == n0
+    big = torch.zeros((600, 7), dtype=torch.float32, device="cuda")
+    lib = p2r._lib.library()
+    rc = lib.p2r_mlp_grads(m.handle, big.data_ptr(), tt.data_ptr(), 600, None, None, None)
+    assert rc == p2r.P2R_ENOSPACE
+    rc = lib.p2r_mlp_train_step(m.handle, big.data_ptr(), tt.data_ptr(), 600, 1e-3, None, None)
+    assert rc == p2r.P2R_ENOSPACE
+    assert p2r.device_allocations() == n0
 
 
 @pytest.fixture(scope="module")
@@ -159,3 +237,4 @@ def test_learned_fit_matches_oracle(ctx, trained, W):
     tl = 4099 * len(d["surf"])
     print(f"W={W}: helix evaluations per track-layer: learned {ev_l / tl:.3f}, plain {ev_p / tl:.3f}; {rep}",
           flush=True)
+    assert ev_l < ev_p

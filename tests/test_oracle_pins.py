@@ -508,3 +508,57 @@ def test_mlp_features_reduce_to_geometry():
         assert sl[i] == pytest.approx(oracle.path(par[i], 1.0, 0.0, 0, R[i]), rel=1e-12)
     assert mlp.proposal(np.zeros(50), sl) == pytest.approx(sl)
     assert f[:, 0] == pytest.approx(np.hypot(par[:, 0], par[:, 1]) / R)
+
+
+def test_mlp_forward_hand_network():
+    """A network set by hand, evaluated by hand: two hidden units pass x0 + 0.5
+    and -x1 + 0.5 through ReLU, the second layer copies them, the output
+    weighs them 2 and 3 and adds 0.25."""
+    p = {k: np.zeros(s) for k, s in (("W1", (64, 7)), ("b1", 64), ("W2", (64, 64)), ("b2", 64),
+                                      ("W3", (1, 64)), ("b3", 1))}
+    p["W1"][0, 0], p["W1"][1, 1] = 1.0, -1.0
+    p["b1"][:2] = 0.5
+    p["W2"][0, 0] = p["W2"][1, 1] = 1.0
+    p["W3"][0, :2] = [2.0, 3.0]
+    p["b3"][0] = 0.25
+    x = np.array([[1.0, -2.0, 3, 0, 0, 0, 0],     # h = (1.5, 2.5): y = 3 + 7.5 + 0.25
+                  [-1.0, 2.0, 0, 0, 0, 0, 0],     # h = (0, 0): both clipped, y = b3
+                  [0.25, 0.25, 0, 0, 0, 0, 9]])   # h = (0.75, 0.25): y = 1.5 + 0.75 + 0.25
+    for bf16 in (False, True):                    # every value here is exact in bfloat16
+        y, c = mlp.forward(p, x, bf16=bf16)
+        assert y == pytest.approx([10.75, 0.25, 2.5], abs=0)
+        assert c["h1"][0, :2] == pytest.approx([1.5, 2.5], abs=0) and not c["h1"][:, 2:].any()
+
+
+def test_mlp_features_closed_forms():
+    """All seven features on states whose straight-line path is known in
+    closed form, and their rotation and charge symmetries."""
+    R, r0, ipt, bz = 50.0, 30.0, 2.0, 3.8
+    w = -2.99792458e-3 * bz * ipt                  # q = +1: omega = -q c B / pT in 1/cm (c = 0.299792458 GeV / (T m))
+    cases = [
+        # at the origin: s_line = R
+        ([0.0, 0.0, 0.0, ipt, 0.7, 1.0], [0.0, 0.0, 0.0, w * R, 1.0, w * R, 0.0]),
+        # on the x axis, moving radially: b = r0, a = 0, s_line = R - r0
+        ([r0, 0.0, 0.0, ipt, 0.0, 1.0], [r0 / R, r0 / R, 0.0, w * R, (R - r0) / R, w * (R - r0), 0.0]),
+        # on the x axis, moving along +y: b = 0, a = -r0, s_line = sqrt(R^2 - r0^2)
+        ([r0, 0.0, 0.0, ipt, np.pi / 2, 1.0],
+         [r0 / R, 0.0, -r0 / R, w * R, 40.0 / R, w * 40.0, -w * r0]),
+    ]
+    for par, exp in cases:
+        f, sl = mlp.features(np.array([par]), np.array([1.0]), np.array([R]), bz=bz)
+        assert f[0] == pytest.approx(exp, rel=1e-12, abs=1e-12)
+    g = np.random.default_rng(12)
+    par = np.array([rstate(g, r0=(0, 20))[0] for _ in range(40)])
+    Rs = g.uniform(25, 100, 40)
+    f, sl = mlp.features(par, np.ones(40), Rs)
+    # rotating the state about the z axis changes no feature
+    for a in (0.3, -2.0):
+        rp = par.copy()
+        rp[:, 0] = np.cos(a) * par[:, 0] - np.sin(a) * par[:, 1]
+        rp[:, 1] = np.sin(a) * par[:, 0] + np.cos(a) * par[:, 1]
+        rp[:, 4] = par[:, 4] + a
+        assert mlp.features(rp, np.ones(40), Rs)[0] == pytest.approx(f, rel=1e-9, abs=1e-12)
+    # the opposite charge flips exactly the curvature features (3, 5, 6)
+    fm = mlp.features(par, -np.ones(40), Rs)[0]
+    sign = np.array([1, 1, 1, -1, 1, -1, -1])
+    assert fm == pytest.approx(f * sign, rel=1e-12, abs=1e-15)
