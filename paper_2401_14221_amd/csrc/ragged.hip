@@ -367,7 +367,7 @@ __device__ __forceinline__ void fit_block(const RaggedLaunch& a, const Params& P
                 if (type == 0) out = step_cylinder<T, false, false>(st, v, m, V, P, c2, newton_tol(P.tol, v), T(NAN));
                 else if (type == 1) out = step_plane<T, false>(st, v, m, V, P, c2);
                 else out.flags = ST_BAD_INPUT;
-                if (out.updated) update_step<T>(st, m, V, P, c2, out);
+                if (out.updated) update_step<T>(st, m, V, P, c2, out, type);
             }
             flags |= out.flags;
             if (out.updated) { ++nused; chi2 += c2; }

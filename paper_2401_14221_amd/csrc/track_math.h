@@ -980,6 +980,183 @@ __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3]
     return res;
 }
 
+// The 3D-hit update taken in the surface frame.  After the transport the
+// state lies on the surface, so the position block of C' has the surface
+// normal n as a null direction: C' H^T has no component along n.  With the
+// orthonormal frame (t1, t2, n) of the crossing point -- cylinder: t1 =
+// (-s, c, 0), t2 = z, n = (c, s, 0), (c, s) = (x, y) / r; plane z = Z: t1 = x,
+// t2 = y, n = z -- the 3x3 innovation covariance is
+//   S = [[A + Vtt, Vtn], [Vtn^T, Vnn]],  A = [t1 t2]^T C'_pos [t1 t2],
+// and block elimination of its n row (a Schur complement of Vnn) gives the
+// same update as the 3x3 one in exact arithmetic:
+//   V^ = Vtt - Vtn Vtn^T / Vnn,  r^ = r_t - Vtn r_n / Vnn,
+//   S^ = A + V^ (2x2),  K = C' H^T S^-1 = P S^^-1 [I | -Vtn / Vnn],
+//   p+ = p' + P S^^-1 r^,  C+ = C' - P S^^-1 P^T (Joseph form below),
+//   chi2 = r^T S^-1 r = r^^T S^^-1 r^ + r_n^2 / Vnn   (3 degrees of freedom),
+// with P = C' [t1 t2] (6x2).  This is the 2x2 update of kalman_update_2d in
+// the crossing point's frame with the measurement covariance and residual
+// corrected for the normal component, at about two thirds of the cost of
+// the 3x3 algebra.  KIND 0: cylinder, 1: plane, 2: chosen per lane by
+// `kind` (kernels whose lanes meet both in one row share one update).
+// Skip rules, fallback modes and the zero-gain trick are those of
+// kalman_update; the FP32 PD test is on S^ (and Vnn > 0), and the FP64
+// fallback runs the 3x3 update in FP64.
+template <typename T, int KIND>
+__device__ __forceinline__ uint32_t kalman_update_surf(StateT<T>& st, const T m[3], const T V[6],
+                                                       const Params& P, T& chi2, uint32_t& flags,
+                                                       int kind = KIND) {
+    constexpr bool F32 = sizeof(T) == sizeof(float);
+    T* c = st.c;
+    // frame: t1 = (a0, a1, 0), t2 = (0, b1, b2), n = (n0, n1, n2)
+    T a0, a1, b1, b2, n0, n1, n2;
+    if constexpr (KIND == 1) {
+        a0 = T(1); a1 = T(0); b1 = T(1); b2 = T(0); n0 = T(0); n1 = T(0); n2 = T(1);
+    } else {
+        const T ir = rcp_(sqrt_start_(fma_(st.p[0], st.p[0], st.p[1] * st.p[1])));
+        const T cc = st.p[0] * ir, ss = st.p[1] * ir;
+        if constexpr (KIND == 0) {
+            a0 = -ss; a1 = cc; b1 = T(0); b2 = T(1); n0 = cc; n1 = ss; n2 = T(0);
+        } else {
+            const bool pl = kind == 1;
+            a0 = pl ? T(1) : -ss; a1 = pl ? T(0) : cc;
+            b1 = pl ? T(1) : T(0); b2 = pl ? T(0) : T(1);
+            n0 = pl ? T(0) : cc; n1 = pl ? T(0) : ss; n2 = pl ? T(1) : T(0);
+        }
+    }
+    // projections of a 3-vector on t1, t2, n (structural zeros folded)
+    auto on_t1 = [&](T vx, T vy, T vz) -> T {
+        if constexpr (KIND == 1) return vx;
+        else return fma_(a0, vx, a1 * vy);
+    };
+    auto on_t2 = [&](T vx, T vy, T vz) -> T {
+        if constexpr (KIND == 0) return vz;
+        else if constexpr (KIND == 1) return vy;
+        else return fma_(b1, vy, b2 * vz);
+    };
+    auto on_n = [&](T vx, T vy, T vz) -> T {
+        if constexpr (KIND == 0) return fma_(n0, vx, n1 * vy);
+        else if constexpr (KIND == 1) return vz;
+        else return fma_(n0, vx, fma_(n1, vy, n2 * vz));
+    };
+    // V t1, V t2, V n (columns of the 3x3 V), then the frame blocks
+    const T Vt1x = on_t1(V[0], V[1], V[3]), Vt1y = on_t1(V[1], V[2], V[4]), Vt1z = on_t1(V[3], V[4], V[5]);
+    const T Vt2x = on_t2(V[0], V[1], V[3]), Vt2y = on_t2(V[1], V[2], V[4]), Vt2z = on_t2(V[3], V[4], V[5]);
+    const T vtt00 = on_t1(Vt1x, Vt1y, Vt1z);
+    const T vtt01 = on_t2(Vt1x, Vt1y, Vt1z);
+    const T vtt11 = on_t2(Vt2x, Vt2y, Vt2z);
+    const T vtn0 = on_n(Vt1x, Vt1y, Vt1z);
+    const T vtn1 = on_n(Vt2x, Vt2y, Vt2z);
+    const T vnn = on_n(on_n(V[0], V[1], V[3]), on_n(V[1], V[2], V[4]), on_n(V[3], V[4], V[5]));
+    const T ivnn = rcp_(vnn);
+    const T g0 = vtn0 * ivnn, g1 = vtn1 * ivnn;
+    const T v00 = fma_(-g0, vtn0, vtt00);
+    const T v01 = fma_(-g0, vtn1, vtt01);
+    const T v11 = fma_(-g1, vtn1, vtt11);
+    // P = C' [t1 t2]: the rows' position parts projected
+    T P0[6], P1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        P0[i] = on_t1(c[I21(i, 0)], c[I21(i, 1)], c[I21(i, 2)]);
+        P1[i] = on_t2(c[I21(i, 0)], c[I21(i, 1)], c[I21(i, 2)]);
+    }
+    const T S00 = on_t1(P0[0], P0[1], P0[2]) + v00;
+    const T S01 = on_t2(P0[0], P0[1], P0[2]) + v01;
+    const T S11 = on_t2(P1[0], P1[1], P1[2]) + v11;
+    const T det = fma_(S00, S11, -S01 * S01);
+    const T tau = F32 ? T(PD_TAU32) : T(PD_TAU_F64_FIT);
+    const bool pd = vnn > T(0) && S00 > T(0) && det > tau * S00 * S11;
+    T id = rcp_(det);
+    T Si00 = S11 * id, Si01 = -S01 * id, Si11 = S00 * id;
+    uint32_t res = 0;
+    bool done = false;
+    if constexpr (!F32) {
+        if (!pd) res = ST_S_NOT_PD;
+    } else if (P.fp64_fallback == 2 || !pd) {
+        if (!P.fp64_fallback) {
+            res = ST_S_NOT_PD;
+        } else {
+            flags |= ST_FP64_FALLBACK;
+            if (P.fp64_fallback != 1) {
+                Fp64Io io;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) io.p[k] = (double)st.p[k] + (double)st.lo[k];
+#pragma unroll
+                for (int k = 0; k < 21; ++k) io.c[k] = st.c[k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) io.m[k] = m[k];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) io.V[k] = V[k];
+                io.chi2 = (float)chi2;
+                res = kalman_update_fp64(&io, P.chi2_cut);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    st.p[k] = (float)io.p[k];
+                    st.lo[k] = k == 3 ? 0.0f : (float)(io.p[k] - (double)st.p[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 21; ++k) st.c[k] = io.c[k];
+                chi2 = io.chi2;
+                done = true;
+            } else {
+                Inv2Io io{(float)S00, (float)S01, (float)S11, 0.0f, 0.0f, 0.0f};
+                if (!(vnn > T(0)) || !inv2_fp64(&io)) res = ST_S_NOT_PD;
+                Si00 = io.i00;
+                Si01 = io.i01;
+                Si11 = io.i11;
+            }
+        }
+    }
+    // residuals: along the surface (corrected for the normal one) and normal
+    const T dx = residual_of(st, 0, m[0]), dy = residual_of(st, 1, m[1]), dz = residual_of(st, 2, m[2]);
+    const T rn = on_n(dx, dy, dz);
+    const T r0 = fma_(-g0, rn, on_t1(dx, dy, dz));
+    const T r1 = fma_(-g1, rn, on_t2(dx, dy, dz));
+    T w0 = fma_(Si00, r0, Si01 * r1);
+    T w1 = fma_(Si01, r0, Si11 * r1);
+    const T c2 = fma_(r0, w0, fma_(r1, w1, rn * rn * ivnn));
+    if (res == 0 && !done && P.chi2_cut > 0.0f && c2 > T(P.chi2_cut)) res = ST_CHI2_CUT;
+    const bool apply = res == 0 && !done;
+    if (apply) chi2 = c2;
+    w0 = apply ? w0 : T(0);
+    w1 = apply ? w1 : T(0);
+    Si00 = apply ? Si00 : T(0);
+    Si01 = apply ? Si01 : T(0);
+    Si11 = apply ? Si11 : T(0);
+    T K0[6], K1[6], KV0[6], KV1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        K0[i] = fma_(P0[i], Si00, P1[i] * Si01);
+        K1[i] = fma_(P0[i], Si01, P1[i] * Si11);
+        KV0[i] = fma_(K0[i], v00, K1[i] * v01);
+        KV1[i] = fma_(K0[i], v01, K1[i] * v11);
+        const T dp = fma_(P0[i], w0, P1[i] * w1);
+        if (i == 3) st.p[i] += dp;
+        else add_to(st, i, dp);
+    }
+    // M = C' - K P^T (entries (i, l) with l <= i, and l < 3), D = K V^ - M [t1 t2],
+    // C+ = M + D K^T: the Joseph form with the 2x2 V^
+    T M[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int l = 0; l < 6; ++l)
+            if (l <= i || l < 3) M[i][l] = fma_(-K0[i], P0[l], fma_(-K1[i], P1[l], c[I21(i, l)]));
+    T D0[6], D1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        D0[i] = KV0[i] - on_t1(M[i][0], M[i][1], M[i][2]);
+        D1[i] = KV1[i] - on_t2(M[i][0], M[i][1], M[i][2]);
+    }
+    T n[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int l = 0; l <= i; ++l) n[I21(i, l)] = fma_(D0[i], K0[l], fma_(D1[i], K1[l], M[i][l]));
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c[k] = n[k];
+    return res;
+}
+
 __device__ __noinline__ uint32_t kalman_update_2d_fp64(Fp64Io2* io, float chi2_cut) {
     StateT<double> sd;
     for (int k = 0; k < 6; ++k) sd.p[k] = io->p[k];   // already with the low parts
@@ -1131,7 +1308,7 @@ __device__ __forceinline__ StepOut step_cylinder(StateT<T>& st, T R, const T m[3
     }
     uint32_t u;
     if constexpr (U2D) u = kalman_update_2d(st, m, V, P, chi2, o.flags);
-    else u = kalman_update(st, m, V, P, chi2, o.flags);
+    else u = kalman_update_surf<T, 0>(st, m, V, P, chi2, o.flags);
     o.flags |= u;
     o.updated = (u == 0);
     wrap_phi_state(st);
@@ -1168,7 +1345,7 @@ __device__ __forceinline__ StepOut step_plane(StateT<T>& st, T Z, const T m[3], 
         o.updated = true;
         return o;
     }
-    uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
+    uint32_t u = kalman_update_surf<T, 1>(st, m, V, P, chi2, o.flags);
     o.flags |= u;
     o.updated = (u == 0);
     wrap_phi_state(st);
@@ -1176,11 +1353,12 @@ __device__ __forceinline__ StepOut step_plane(StateT<T>& st, T Z, const T m[3], 
     return o;
 }
 
-// The update that ends a step taken with UPDATE = false (3D hit).
+// The update that ends a step taken with UPDATE = false (3D hit) on a
+// surface of type `kind` (0 cylinder, 1 plane).
 template <typename T>
 __device__ __forceinline__ void update_step(StateT<T>& st, const T m[3], const T V[6], const Params& P,
-                                            T& chi2, StepOut& o) {
-    const uint32_t u = kalman_update(st, m, V, P, chi2, o.flags);
+                                            T& chi2, StepOut& o, int kind) {
+    const uint32_t u = kalman_update_surf<T, 2>(st, m, V, P, chi2, o.flags, kind);
     o.flags |= u;
     o.updated = (u == 0);
     wrap_phi_state(st);

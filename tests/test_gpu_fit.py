@@ -164,11 +164,20 @@ def test_fp64_update_forced_matches(ctx):
             final_surface="plane")
 
 
-def test_fp64_fallback_triggers_on_ill_conditioned_S(ctx):
+def _max_rel(x, r):
+    dpar = np.abs(x["par"] - r["par"])
+    dpar[:, 4] = np.abs(np.angle(np.exp(1j * (x["par"][:, 4] - r["par"][:, 4]))))
+    rel = dpar / np.maximum(np.abs(r["par"]), [1, 1, 1, 1e-30, 1, 1e-30])
+    return rel.max(), (np.abs(x["chi2"] - r["chi2"]) / np.maximum(r["chi2"], 1)).max()
+
+
+def test_normal_resolving_hit_needs_no_fallback(ctx):
     """On the first layer (r = 4 cm) a hit 2e-8 cm^2 wide along the layer normal and 1e-4
-    along the layer gives S a condition number ~5e5: the FP32 test fails and the update
-    runs in FP64, matching the oracle.  (The layer is the innermost one so that the FP32
-    position quantum, ulp(4 cm) = 4.8e-7 cm, stays far below the hit's 1.4e-4 cm.)"""
+    along the layer makes the 3x3 innovation covariance S ill-conditioned (~5e5), but
+    not the surface-frame update, which takes the normal component through the Schur
+    complement of V_nn: no FP64 fallback, and the oracle's (3x3, FP64) result.  (The
+    layer is the innermost one so that the FP32 position quantum, ulp(4 cm) = 4.8e-7 cm,
+    stays far below the hit's 1.4e-4 cm.)"""
     d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=256)
     li = 0
     tr = d["truth"][:, li, :3]
@@ -186,28 +195,53 @@ def test_fp64_fallback_triggers_on_ill_conditioned_S(ctx):
     hc[:, li, 0], hc[:, li, 1], hc[:, li, 2] = Vxy[:, 0, 0], Vxy[:, 1, 0], Vxy[:, 1, 1]
     e = dict(d, hits=hits.astype(np.float32).astype(np.float64), hitcov=hc.astype(np.float32).astype(np.float64))
     r = oracle.fit_event(e, "barrel")
+    g = run_p2r(ctx, e, 64)
+    assert not (g["status"][ok] & p2r.ST_FP64_FALLBACK).any()
+    par_err, chi2_err = _max_rel(g, r)
+    print("normal-resolving hit: max rel par %.2e  max rel chi2 %.2e" % (par_err, chi2_err), flush=True)
+    # the hit resolves the crossing's radial position, which an FP32 solve fixes to
+    # about ulp(4 cm): ~0.5 % of that hit's chi2 term, a few 1e-4 of the parameters
+    assert par_err < 1e-3 and chi2_err < 1e-2
+
+
+def test_fp64_fallback_triggers_on_ill_conditioned_S(ctx):
+    """Tracks whose prior is nearly singular within the first layer's surface: the z and
+    phi uncertainties (1 cm, 0.25 rad) fully correlated, everything else 1e-3 cm or less,
+    so that at r = 4 cm the along-surface position covariance is ~ (t1 + z)(t1 + z)^T;
+    with a first hit 1e-2 cm wide in r-phi and z the 2x2 S^ has condition ~2e4: the
+    FP32 test fails, the update runs in FP64 (the full update by default, or only the
+    inverse) and matches the oracle."""
+    d = ev.make_barrel_event(ev.P2R_PARITY, n_tracks=256)
+    u = np.array([0.0, 0.0, 1.0, 0.0, 0.25, 0.0])
+    Cfull = np.diag([1e-6, 1e-6, 1e-6, 1e-4, 1e-8, 1e-8]) + np.outer(u, u)
+    il = np.tril_indices(6)
+    cov = np.tile(Cfull[il], (256, 1))
+    hc = d["hitcov"].copy()
+    hc[:, 0, 5] = 1e-4
+    e = dict(d, cov=cov.astype(np.float32).astype(np.float64), hitcov=hc)
+    r = oracle.fit_event(e, "barrel")
+    ok = (r["status"] & 0xFF) == 0
+    assert ok.mean() > 0.9
     g = run_p2r(ctx, e, 64)                     # default: whole update in FP64 on fallback
-    st = g["status"]
-    assert (st[ok] & p2r.ST_FP64_FALLBACK).mean() > 0.9
-    # With S this ill-conditioned the limit is no longer the update: the FP32 Jacobian
-    # leaves C' a ~1e-8 relative component (~1e-10 cm^2) along the layer normal, which
-    # a 2e-8 cm^2 hit resolves, moving that hit's chi2 term by ~0.5 %.  Bounds: 1e-3
-    # relative on the parameters, 1e-2 on chi2.
+    assert (g["status"][ok] & p2r.ST_FP64_FALLBACK).mean() > 0.9
     g1 = run_p2r(ctx, e, 64, fp64_fallback=1)
     assert (g1["status"][ok] & p2r.ST_FP64_FALLBACK).mean() > 0.9
     errs = {}
     for name, x in (("full FP64 update", g), ("FP64 inverse only", g1)):
         assert np.all(np.isfinite(x["par"]))
-        dpar = np.abs(x["par"] - r["par"])
-        dpar[:, 4] = np.abs(np.angle(np.exp(1j * (x["par"][:, 4] - r["par"][:, 4]))))
-        rel = dpar / np.maximum(np.abs(r["par"]), [1, 1, 1, 1e-30, 1, 1e-30])
-        errs[name] = (rel.max(), (np.abs(x["chi2"] - r["chi2"]) / np.maximum(r["chi2"], 1)).max())
+        errs[name] = _max_rel({k: x[k][ok] for k in ("par", "chi2")}, {k: r[k][ok] for k in ("par", "chi2")})
         print(name, "max rel par %.2e  max rel chi2 %.2e" % errs[name], flush=True)
-    # measured: full FP64 update 2.0e-4 (par) / 5.5e-3 (chi2), FP64 inverse only
-    # 3.5e-4 / 9.7e-3; the full update, the default, is the more accurate
-    assert errs["full FP64 update"][0] < 1e-3 and errs["full FP64 update"][1] < 1e-2
-    assert errs["FP64 inverse only"][0] < 1e-3 and errs["FP64 inverse only"][1] < 2e-2
-    assert errs["full FP64 update"][1] <= errs["FP64 inverse only"][1]
+    # the default (the whole update in FP64) meets the parity rule, whose bounds the
+    # oracle's FP32 runs widen for these strongly correlated priors (the FP32 steps
+    # after the first layer work on them); the FP64 inverse alone, with FP32 gain and
+    # covariance products, is looser (measured 3.7e-3 / 1.1e-2) and no more accurate
+    rep = compare(g, r, ctx="fallback, full FP64 update")
+    print("full FP64 update:", rep, flush=True)
+    assert errs["FP64 inverse only"][0] < 1e-2 and errs["FP64 inverse only"][1] < 3e-2
+    assert errs["full FP64 update"][0] <= errs["FP64 inverse only"][0]
+    # and without the fallback those updates are skipped as not positive definite
+    g0 = run_p2r(ctx, e, 64, fp64_fallback=0)
+    assert (g0["status"][ok] & p2r.ST_S_NOT_PD).mean() > 0.9
 
 
 def test_empty_and_argument_errors(ctx):
