@@ -2,14 +2,16 @@
 // (CSR), each a cylinder or a plane, with one 3D hit per surface.
 //
 // Schedule (all on the caller's stream, captured once into a HIP graph):
-//   1. rag_reset   zero the key histogram and the work-queue counter
+//   1. rag_reset   zero the key histogram, the key cursors and the
+//                  work-queue counter
 //   2. rag_hist    sort key of every track; per-workgroup histogram in LDS,
 //                  then one global atomic per (workgroup, key)
-//   3. rag_scan    (one workgroup) the first sorted position of every key
-//   4. rag_scatter counting-sort scatter -> perm[sorted position] = track and
-//                  run[sorted position] = its CSR run, ranks from LDS
-//                  atomics, one cursor atomic per (workgroup, key)
-//   5. rag_fit_*   one wave per block of RAG_W sorted tracks: streams the
+//   3. rag_scatter counting-sort scatter -> perm[sorted position] = track and
+//                  run[sorted position] = its CSR run: every workgroup takes
+//                  the first sorted position of each key from a prefix sum
+//                  of the (small) histogram in LDS, its tracks' ranks from
+//                  LDS atomics, and one cursor atomic per (workgroup, key)
+//   4. rag_fit_*   one wave per block of RAG_W sorted tracks: streams the
 //                  block's hits from the CSR arrays through LDS, a chunk of
 //                  surfaces at a time, and fits its 64 tracks (the queue
 //                  variant: a persistent grid whose waves take blocks from an
@@ -35,9 +37,13 @@ __device__ __forceinline__ int track_key(const RaggedLaunch& a, int64_t t) {
     if (L < 0 || L > a.lmax || h0 < 0 || h0 + L > a.n_hits) return invalid;
     const float th = a.par_in[(size_t)t * 6 + 5];
     if (!(th > 0.0f && th < PI_F)) return invalid;
-    const float aeta = asinhf(fabsf(cosf(th) / sinf(th)));
-    int bin = (int)(aeta * (RAG_ETA_BINS / 2.5f));
-    bin = bin < 0 ? 0 : (bin >= RAG_ETA_BINS ? RAG_ETA_BINS - 1 : bin);
+    // |eta| bin of width 2.5 / RAG_ETA_BINS, from |cos theta| = tanh|eta|
+    // against the bin edges tanh(k 2.5 / 8) (the bin only groups tracks, so
+    // the fast cosine's error at an edge does not matter)
+    static_assert(RAG_ETA_BINS == 8, "bin edges below are for 8 bins of 0.3125");
+    const float c = fabsf(__cosf(th));
+    const int bin = (c >= 0.302709729f) + (c >= 0.554599722f) + (c >= 0.73407152f) + (c >= 0.84828364f) +
+                    (c >= 0.915824544f) + (c >= 0.95404526f) + (c >= 0.975136698f);
     return (a.lmax - (int)L) * RAG_ETA_BINS + bin;
 }
 
@@ -48,7 +54,10 @@ __device__ __forceinline__ int key_layers(const RaggedLaunch& a, int k) {
 
 __global__ void rag_reset(RaggedLaunch a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < a.nkeys) a.hist[i] = 0;
+    if (i < a.nkeys) {
+        a.hist[i] = 0;
+        a.base[i] = 0;
+    }
     if (i == 0) a.work[0] = 0;
 }
 
@@ -71,43 +80,46 @@ __global__ void __launch_bounds__(256) rag_hist(RaggedLaunch a) {
         if (lh[k]) atomicAdd(&a.hist[k], lh[k]);
 }
 
-// One workgroup of 1024 threads: base[k] = sum of hist[k'] for k' < k.
-__global__ void __launch_bounds__(1024) rag_scan(RaggedLaunch a) {
-    __shared__ int32_t part[1024];
-    const int tid = threadIdx.x;
-    const int per = (a.nkeys + 1023) / 1024;
-    const int lo = min(tid * per, a.nkeys), hi = min(lo + per, a.nkeys);
-    int32_t s = 0;
-    for (int i = lo; i < hi; ++i) s += a.hist[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int32_t v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int32_t run = tid > 0 ? part[tid - 1] : 0;
-    for (int i = lo; i < hi; ++i) {
-        const int32_t c = a.hist[i];
-        a.base[i] = run;
-        run += c;
-    }
-}
-
-// dynamic LDS: 2 nkeys ints (ranks, workgroup bases)
+// dynamic LDS: 3 nkeys ints (ranks, first sorted positions, workgroup bases)
+// plus 256 partial sums.  base[] holds the keys' cursors (zeroed by
+// rag_reset): a workgroup's tracks of key k go to first[k] + the cursor's
+// value before its atomic add.
 __global__ void __launch_bounds__(256) rag_scatter(RaggedLaunch a) {
     extern __shared__ int32_t sh[];
     int32_t* lh = sh;
     int32_t* off = sh + a.nkeys;
-    for (int k = threadIdx.x; k < a.nkeys; k += blockDim.x) lh[k] = 0;
+    int32_t* first = sh + 2 * a.nkeys;
+    int32_t* part = sh + 3 * a.nkeys;
+    const int tid = threadIdx.x;
+    // exclusive prefix sum of the finished histogram: thread tid sums a
+    // contiguous range of keys, the 256 range sums are scanned in LDS, then
+    // each thread writes its range's first positions
+    const int per = (a.nkeys + 255) / 256;
+    const int lo = min(tid * per, a.nkeys), hi = min(lo + per, a.nkeys);
+    int32_t sum = 0;
+    for (int k = lo; k < hi; ++k) {
+        const int32_t c = a.hist[k];
+        first[k] = sum;
+        sum += c;
+        lh[k] = 0;
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int32_t v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    const int32_t before = tid > 0 ? part[tid - 1] : 0;
+    for (int k = lo; k < hi; ++k) first[k] += before;
     __syncthreads();
     constexpr int PER = RAG_TPB / 256;
     int key[PER], rank[PER];
     const int64_t t0 = (int64_t)blockIdx.x * RAG_TPB;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        const int64_t t = t0 + threadIdx.x + j * 256;
+        const int64_t t = t0 + tid + j * 256;
         key[j] = -1;
         if (t < a.n) {
             key[j] = a.keys[t];
@@ -115,12 +127,12 @@ __global__ void __launch_bounds__(256) rag_scatter(RaggedLaunch a) {
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < a.nkeys; k += blockDim.x)
-        if (lh[k]) off[k] = atomicAdd(&a.base[k], lh[k]);
+    for (int k = tid; k < a.nkeys; k += blockDim.x)
+        if (lh[k]) off[k] = first[k] + atomicAdd(&a.base[k], lh[k]);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        const int64_t t = t0 + threadIdx.x + j * 256;
+        const int64_t t = t0 + tid + j * 256;
         if (key[j] >= 0) {
             const int32_t pos = off[key[j]] + rank[j];
             a.perm[pos] = (int32_t)t;
@@ -419,12 +431,12 @@ rag_fit_queue(RaggedLaunch a, Params P) {
 // e<N> compiled for N waves per SIMD, queue the persistent grid.
 void append_ragged_variants(std::vector<Variant>& v) {
     // the first is the default (the fastest measured on the 10^6-track workload)
-    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b16_pf", RAG_GRID(4, 16, true, 0, float, false), false, false, false, true});
     v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b16", RAG_GRID(4, 16, false, 0, float, false), false, false, false, true});
+    v.push_back(Variant{2, RAG_W, 4, 4, "rag_fit_c4b16_e4", RAG_GRID(4, 16, false, 4, float, false), false, false, false, true});
+    v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b16_pf", RAG_GRID(4, 16, true, 0, float, false), false, false, false, true});
     v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b8", RAG_GRID(4, 8, false, 0, float, false), false, false, false, true});
     v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b4", RAG_GRID(4, 4, false, 0, float, false), false, false, false, true});
     v.push_back(Variant{2, RAG_W, 0, 8, "rag_fit_c8b16", RAG_GRID(8, 16, false, 0, float, false), false, false, false, true});
-    v.push_back(Variant{2, RAG_W, 4, 4, "rag_fit_c4b16_e4", RAG_GRID(4, 16, false, 4, float, false), false, false, false, true});
     v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_c4b16_queue", RAG_QUEUE(4, 16, false, 0), false, false, false, false});
     v.push_back(Variant{2, RAG_W, 0, 4, "rag_fit_f64", RAG_GRID(4, 16, false, 2, double, false), false, true, false, true});
     v.push_back(Variant{2, RAG_W, 4, 4, "rag_fit_2d", RAG_GRID(4, 16, false, 4, float, true), false, false, true, true});
@@ -529,8 +541,7 @@ hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& 
     const int64_t nwg = ((int64_t)a.n + RAG_TPB - 1) / RAG_TPB;
     if (nwg > 0) {
         hipLaunchKernelGGL(rag_hist, dim3((unsigned)nwg), dim3(tb), lds_keys, s, aa);
-        hipLaunchKernelGGL(rag_scan, dim3(1), dim3(1024), 0, s, aa);
-        hipLaunchKernelGGL(rag_scatter, dim3((unsigned)nwg), dim3(tb), 2 * lds_keys, s, aa);
+        hipLaunchKernelGGL(rag_scatter, dim3((unsigned)nwg), dim3(tb), 3 * lds_keys + sizeof(int32_t) * tb, s, aa);
         void* args[] = {&aa, &pp};
         hipError_t e = hipLaunchKernel(v.fn, dim3(v.per_block ? a.nb : a.grid), dim3(RAG_W), args, 0, s);
         if (e != hipSuccess) return e;
