@@ -27,7 +27,14 @@ UNIT = "track-layers/s"
 HBM_PEAK_GBPS = 8000.0
 # FP32 vector peak of MI355X (published; counts an FMA as 2 flops)
 FP32_PEAK_TFLOPS = 157.3
-# algorithmic work per track-layer ("Roofline of the fit kernel")
+# dense BF16 matrix-core peak of MI355X, and the path-length network's work per
+# evaluation (7 -> 64 -> 64 -> 1: 4,608 multiply-adds, 2 flops each)
+BF16_PEAK_TFLOPS = 2500.0
+MLP_FLOP_PER_EVAL = 2 * (7 * 64 + 64 * 64 + 64)
+# algorithmic work per track-layer of the textbook method (3x3 update, Joseph
+# covariance, J C J^T with J's structural zeros, two helix evaluations per
+# cylinder crossing; FMA = 2 flops): the rate is quoted in these flops whatever
+# cheaper form of the same arithmetic the kernel uses
 P2R_FLOP_PER_TL = 1261.0
 P2Z_FLOP_PER_TL = 930.0
 TRACK_BYTES = 28 * 4 * 2 + 4 + 4      # record in + record out + chi2 + status
@@ -402,10 +409,12 @@ def learned_leg(ctx, args, stream, ev, p2r, dev):
     torch.cuda.synchronize()                  # the packing ran on the current stream
     res = {"workload": cfg.name}
     outs = {}
-    for name, m in (("plain", None), ("learned", mlp)):
+    # the three starts of the helix-to-cylinder solve on the same workload:
+    # straight line, closed-form FP32 crossing, learned proposal
+    for name, m, cyl_start in (("plain", None, 0), ("closed_form", None, 1), ("learned", mlp, 0)):
         o = (torch.empty_like(trk), torch.empty(n, dtype=torch.float32, device=dev),
              torch.empty(n, dtype=torch.int32, device=dev))
-        opts = p2r._lib.default_opts(width=W)
+        opts = p2r._lib.default_opts(width=W, cyl_start=cyl_start)
         if m is not None:
             opts.mlp = m.handle.value
 
@@ -430,9 +439,15 @@ def learned_leg(ctx, args, stream, ev, p2r, dev):
     scale = torch.maximum(par_p.abs(), torch.tensor([1, 1, 1, 0, 1, 0], dtype=torch.float32, device=dev))
     res["max_rel_diff_learned_vs_plain"] = float((dpar / scale.clamp_min(1e-30)).max())
     res["speed_ratio_learned_over_plain"] = res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"]
-    log(f"learned: {res['learned']['ms_per_step']:.3f} ms vs plain {res['plain']['ms_per_step']:.3f} ms; "
-        f"evals/track-layer {res['learned']['helix_evals_per_track_layer']:.3f} vs "
-        f"{res['plain']['helix_evals_per_track_layer']:.3f}")
+    res["speed_ratio_closed_form_over_plain"] = res["plain"]["ms_per_step"] / res["closed_form"]["ms_per_step"]
+    # the network's matrix-core work alone, at the dense BF16 peak: a floor on
+    # the learned start's added time, however its kernel is written
+    res["mlp_mfma_floor_ms"] = n * L * MLP_FLOP_PER_EVAL / (BF16_PEAK_TFLOPS * 1e12) * 1e3
+    log(f"learned: {res['learned']['ms_per_step']:.3f} ms vs plain {res['plain']['ms_per_step']:.3f} ms vs "
+        f"closed-form start {res['closed_form']['ms_per_step']:.3f} ms; evals/track-layer "
+        f"{res['learned']['helix_evals_per_track_layer']:.3f} vs {res['plain']['helix_evals_per_track_layer']:.3f} "
+        f"vs {res['closed_form']['helix_evals_per_track_layer']:.3f}; MLP matrix-core floor "
+        f"{res['mlp_mfma_floor_ms']:.3f} ms")
     return res
 
 
