@@ -7,8 +7,14 @@
  * surface in a uniform field B z-hat, transport the 6x6 covariance with the
  * Jacobian (C' = J C J^T), and Kalman-update with the surface's 3D hit
  * (innovation covariance S, gain, state and Joseph-form covariance update,
- * chi2).  One GPU lane handles one track; the arithmetic is FP32, with the
- * update taken to FP64 when the FP32 positive-definiteness test of S fails.
+ * chi2 with 3 degrees of freedom).  The update is computed in the surface
+ * frame of the crossing point: the transported position covariance has the
+ * surface normal as a null direction, so the 3x3 update equals a 2x2 one with
+ * the hit covariance and residual corrected for their normal component (a
+ * Schur complement) plus the normal residual's chi2 term.  One GPU lane
+ * handles one track; the arithmetic is FP32 with a compensated (two-part)
+ * state, and the update is taken to FP64 when the FP32 positive-definiteness
+ * test fails.
  *
  * Units: cm, GeV, tesla, radians.  Curvature omega = -q * 2.99792458e-3 * B / pT
  * [1/cm]; positive tracks turn clockwise seen from +z.  Path lengths are
@@ -89,10 +95,11 @@ typedef struct {
     float newton_tol_cm;     /* |r(s) - R| tolerance, raised to 2 ulp(R) */
     int32_t newton_max_iter; /* helix evaluations before NEWTON_FAIL */
     float chi2_cut;          /* <= 0: off; else skip updates with chi2 > cut */
-    int32_t fp64_fallback;   /* when the FP32 PD test of S fails: 3 = the whole update (inverse,
-                                gain, Joseph covariance) in FP64; 1 = only the 3x3 inverse in
-                                FP64; 0 = skip the update; 2 = the FP64 update for every
-                                surface (testing) */
+    int32_t fp64_fallback;   /* when the FP32 PD test (on the pivots of the surface-frame 2x2 S,
+                                and V_nn > 0) fails: 3 = the whole 3x3 update (inverse, gain,
+                                Joseph covariance) in FP64; 1 = only the 2x2 inverse in FP64;
+                                0 = skip the update; 2 = the FP64 update for every surface
+                                (testing) */
     int32_t width;           /* AoSoA width for p2r: 0 = context's tuned width, or 32/64/128/256 */
     const void* mlp;         /* NULL: plain start; else a p2r_mlp handle (learned start, p2r only) */
     int32_t use_graph;       /* fit_tracks_batched: 1 = capture once per shape and replay a HIP
