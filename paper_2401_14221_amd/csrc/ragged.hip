@@ -30,12 +30,12 @@ namespace p2r {
 
 int ragged_nkeys(int lmax) { return (lmax + 1) * RAG_ETA_BINS + 1; }
 
-__device__ __forceinline__ int track_key(const RaggedLaunch& a, int64_t t) {
-    const int64_t h0 = a.offsets[t];
-    const int64_t L = a.offsets[t + 1] - h0;
+// The sort key of a track from its CSR offsets h0 = offsets[t],
+// h1 = offsets[t + 1] and its theta.
+__device__ __forceinline__ int track_key(const RaggedLaunch& a, int64_t h0, int64_t h1, float th) {
+    const int64_t L = h1 - h0;
     const int invalid = a.nkeys - 1;
     if (L < 0 || L > a.lmax || h0 < 0 || h0 + L > a.n_hits) return invalid;
-    const float th = a.par_in[(size_t)t * 6 + 5];
     if (!(th > 0.0f && th < PI_F)) return invalid;
     // |eta| bin of width 2.5 / RAG_ETA_BINS, from |cos theta| = tanh|eta|
     // against the bin edges tanh(k 2.5 / 8) (the bin only groups tracks, so
@@ -66,11 +66,26 @@ __global__ void __launch_bounds__(256) rag_hist(RaggedLaunch a) {
     extern __shared__ int32_t lh[];
     for (int k = threadIdx.x; k < a.nkeys; k += blockDim.x) lh[k] = 0;
     __syncthreads();
+    // every load first: a load placed after a key store (which might alias
+    // it, for all the compiler knows) would wait for that store
+    constexpr int PER = RAG_TPB / 256;
     const int64_t t0 = (int64_t)blockIdx.x * RAG_TPB;
-    for (int i = threadIdx.x; i < RAG_TPB; i += blockDim.x) {
-        const int64_t t = t0 + i;
+    int64_t h0[PER], h1[PER];
+    float th[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int64_t t = t0 + threadIdx.x + j * 256;
         if (t < a.n) {
-            const int key = track_key(a, t);
+            h0[j] = a.offsets[t];
+            h1[j] = a.offsets[t + 1];
+            th[j] = a.par_in[(size_t)t * 6 + 5];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int64_t t = t0 + threadIdx.x + j * 256;
+        if (t < a.n) {
+            const int key = track_key(a, h0[j], h1[j], th[j]);
             a.keys[t] = key;
             atomicAdd(&lh[key], 1);
         }
@@ -116,16 +131,21 @@ __global__ void __launch_bounds__(256) rag_scatter(RaggedLaunch a) {
     __syncthreads();
     constexpr int PER = RAG_TPB / 256;
     int key[PER], rank[PER];
+    int64_t h0[PER];
     const int64_t t0 = (int64_t)blockIdx.x * RAG_TPB;
+    // the keys and CSR offsets are loaded before any store (see rag_hist)
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int64_t t = t0 + tid + j * 256;
         key[j] = -1;
         if (t < a.n) {
             key[j] = a.keys[t];
-            rank[j] = atomicAdd(&lh[key[j]], 1);
+            h0[j] = a.offsets[t];
         }
     }
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+        if (key[j] >= 0) rank[j] = atomicAdd(&lh[key[j]], 1);
     __syncthreads();
     for (int k = tid; k < a.nkeys; k += blockDim.x)
         if (lh[k]) off[k] = first[k] + atomicAdd(&a.base[k], lh[k]);
@@ -139,7 +159,7 @@ __global__ void __launch_bounds__(256) rag_scatter(RaggedLaunch a) {
             // the track's CSR run in sorted order, so that the fit reads it
             // sequentially instead of gathering offsets[t]
             const int L = key_layers(a, key[j]);
-            a.run[pos] = key[j] < a.nkeys - 1 ? (a.offsets[t] | ((int64_t)L << RAG_RUN_SHIFT)) : (int64_t)-1;
+            a.run[pos] = key[j] < a.nkeys - 1 ? (h0[j] | ((int64_t)L << RAG_RUN_SHIFT)) : (int64_t)-1;
         }
     }
 }
