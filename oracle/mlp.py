@@ -8,9 +8,10 @@ the path-length proposal consumes, and the residual target it predicts.
 With ``bf16=True`` the operands that go through the matrix cores are
 rounded to bfloat16 (round to nearest even) before an FP64 product: x and
 W1 (layer 1), h1 and W2 (layer 2), dz2 and W2 (dh1 = W2^T dz2 in the
-backward pass).  Biases, the last layer and the weight-gradient sums stay
-unrounded.  This reproduces what the matrix cores consume and leaves only
-the accumulation order as a difference.
+backward pass), dz2 and h1 (dW2 = dz2^T h1), dz1 and x (dW1 = dz1^T x).
+Biases, the last layer and the bias-gradient sums stay unrounded.  This
+reproduces what the matrix cores consume and leaves only the accumulation
+order as a difference.
 """
 from __future__ import annotations
 
@@ -59,11 +60,11 @@ def loss_and_grads(params, x, t, bf16=False):
     g["b3"] = np.array([dy.sum()])
     dh2 = dy[:, None] * W3[0][None, :]
     dz2 = dh2 * (c["z2"] > 0)
-    g["W2"] = dz2.T @ c["h1"]
+    g["W2"] = _op(dz2, bf16).T @ _op(c["h1"], bf16)
     g["b2"] = dz2.sum(0)
     dh1 = _op(dz2, bf16) @ _op(W2, bf16)
     dz1 = dh1 * (c["z1"] > 0)
-    g["W1"] = dz1.T @ c["x"]
+    g["W1"] = _op(dz1, bf16).T @ _op(c["x"], bf16)
     g["b1"] = dz1.sum(0)
     return loss, g
 

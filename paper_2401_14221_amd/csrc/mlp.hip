@@ -4,7 +4,8 @@
 //             cores, FP32 accumulation, FP32 biases and last layer.
 //   backward: dy = 2 (y - t) / B (mean squared error), dz2 = dy w3 * [z2 > 0],
 //             dh1 = W2^T dz2 on the matrix cores (BF16 W2, dz2), dz1 = dh1 * [z1 > 0];
-//             weight gradients dW2 = dz2 h1^T, dW1 = dz1 x^T and the bias and
+//             weight gradients dW2 = dz2 h1^T and dW1 = dz1 x^T on the matrix
+//             cores (BF16 dz2, h1, dz1, x; FP32 accumulation), the bias and
 //             last-layer sums in FP32 on the vector units.
 //   Adam on the FP32 master weights, then a fresh BF16 copy.
 #include "mlp.h"
@@ -140,31 +141,55 @@ __global__ void __launch_bounds__(64) mlp_grads_kernel(const MlpWeights* __restr
     for (int k = 0; k < MLP_IN; ++k) T.x[k][l] = f[k];
     T.dy[l] = dy;
     __syncthreads();
-    // weight gradients: lane l owns output row l
-    const int o = l;
-    float gw2[MLP_H];
+    // weight gradients on the matrix cores, contracting over the wave's 64
+    // samples: dW2 = dz2 h1^T (64 x 64) and dW1 = dz1 x^T (64 x 7), BF16
+    // operands and FP32 accumulation.  The A operand of an output row block
+    // comes from that row's [row][sample] tile (lane l: row l % 32, samples
+    // 8 (l / 32) .. + 8 of the K step), the B operand from the columns' tiles
+    // likewise; output element j of lane l is (row blk_row(j), column l % 32).
+    auto tile_bf16 = [&](const float* row, int s0) -> bf16x8 {
+        bf16x8 v;
 #pragma unroll
-    for (int h = 0; h < MLP_H; ++h) gw2[h] = 0.0f;
-    float gb2 = 0.0f, gw3 = 0.0f, gb1 = 0.0f, gb3 = 0.0f;
-    float gw1[MLP_IN];
+        for (int k = 0; k < 8; ++k) v[k] = (__bf16)row[s0 + k];
+        return v;
+    };
+    const bf16x8 zero8 = {};
 #pragma unroll
-    for (int k = 0; k < MLP_IN; ++k) gw1[k] = 0.0f;
-    for (int s = 0; s < 64; ++s) {
-        const float g2 = T.dz2[o][s];
-        const float g1 = T.dz1[o][s];
-        gb2 += g2;
-        gb1 += g1;
+    for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
-        for (int h = 0; h < MLP_H; ++h) gw2[h] = fmaf(g2, T.h1[h][s], gw2[h]);
+        for (int nb = 0; nb < 2; ++nb) {
+            floatx16 acc = {};
 #pragma unroll
-        for (int k = 0; k < MLP_IN; ++k) gw1[k] = fmaf(g1, T.x[k][s], gw1[k]);
-        // h2 = relu(z2) is not in the tiles: w3's gradient from dz2 / w3 is
-        // ill-defined at w3 = 0, so it is accumulated from h2 directly below
+            for (int kc = 0; kc < 4; ++kc) {
+                const int s0 = kc * 16 + 8 * hi;
+                acc = mfma32(tile_bf16(T.dz2[mb * 32 + r32], s0), tile_bf16(T.h1[nb * 32 + r32], s0), acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                grad[OFF_W2 + (mb * 32 + blk_row(j, hi)) * MLP_H + nb * 32 + r32] = acc[j];
+        }
+        // dW1: the B operand's columns are the 7 features (columns 7..31 zero)
+        floatx16 acc = {};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            const int s0 = kc * 16 + 8 * hi;
+            const bf16x8 xb = tile_bf16(T.x[r32 < MLP_IN ? r32 : 0], s0);
+            acc = mfma32(tile_bf16(T.dz1[mb * 32 + r32], s0), r32 < MLP_IN ? xb : zero8, acc);
+        }
+        if (r32 < MLP_IN) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) grad[OFF_W1 + (mb * 32 + blk_row(j, hi)) * MLP_IN + r32] = acc[j];
+        }
     }
-#pragma unroll
-    for (int h = 0; h < MLP_H; ++h) grad[OFF_W2 + o * MLP_H + h] = gw2[h];
-#pragma unroll
-    for (int k = 0; k < MLP_IN; ++k) grad[OFF_W1 + o * MLP_IN + k] = gw1[k];
+    // bias gradients: lane l sums row l of dz2 and dz1 over the samples (FP32)
+    const int o = l;
+    float gb2 = 0.0f, gb1 = 0.0f, gb3 = 0.0f;
+    for (int s = 0; s < 64; ++s) {
+        gb2 += T.dz2[o][s];
+        gb1 += T.dz1[o][s];
+    }
+    // h2 = relu(z2) is not in the tiles: w3's gradient from dz2 / w3 is
+    // ill-defined at w3 = 0, so it is accumulated from h2 directly below
     grad[OFF_B2 + o] = gb2;
     grad[OFF_B1 + o] = gb1;
     // w3 and b3: sum over the samples of dy * h2 (each lane has 32 hidden units of 2 samples)
@@ -184,7 +209,6 @@ __global__ void __launch_bounds__(64) mlp_grads_kernel(const MlpWeights* __restr
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) gb3 += __shfl_xor(gb3, off);
     if (l == 0) grad[OFF_B3] = gb3;
-    (void)gw3;
 }
 
 __global__ void mlp_reduce_kernel(const float* __restrict__ part, int nblk, float* __restrict__ g,

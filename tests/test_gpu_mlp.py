@@ -77,11 +77,14 @@ def _grad_term_bounds(p, x, t):
     dz2 = dy[:, None] * np.abs(W3[0])[None, :] * (c["z2"] > 0)
     dz1 = (np.abs(omlp.bf16_round(dz2)) @ np.abs(omlp.bf16_round(W2))) * (c["z1"] > 0)
     h1, h2, xx = np.abs(c["h1"]), np.abs(c["h2"]), np.abs(c["x"])
-    S = dict(W3=(dy @ h2)[None, :], b3=np.array([dy.sum()]), W2=dz2.T @ h1, b2=dz2.sum(0),
-             W1=dz1.T @ xx, b1=dz1.sum(0))
+    # the weight gradients' operands go through the matrix cores in BF16
+    r = omlp.bf16_round
+    dz2r, h1r, dz1r, xr = np.abs(r(dz2)), np.abs(r(h1)), np.abs(r(dz1)), np.abs(r(xx))
+    S = dict(W3=(dy @ h2)[None, :], b3=np.array([dy.sum()]), W2=dz2r.T @ h1r, b2=dz2.sum(0),
+             W1=dz1r.T @ xr, b1=dz1.sum(0))
     M = dict(W3=(dy[:, None] * h2).max(0)[None, :], b3=np.array([dy.max()]),
-             W2=(dz2[:, :, None] * h1[:, None, :]).max(0), b2=dz2.max(0),
-             W1=(dz1[:, :, None] * xx[:, None, :]).max(0), b1=dz1.max(0))
+             W2=(dz2r[:, :, None] * h1r[:, None, :]).max(0), b2=dz2.max(0),
+             W1=(dz1r[:, :, None] * xr[:, None, :]).max(0), b1=dz1.max(0))
     return S, M
 
 
