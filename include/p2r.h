@@ -290,7 +290,7 @@ typedef struct p2r_mlp p2r_mlp;
  * initialises the weights from `seed` (W1, W2 uniform in +-sqrt(6 / fan_in),
  * w3 the same scaled by 0.1, biases 0; a counter-based hash of the seed and
  * the parameter index); synchronises. */
-int p2r_mlp_create(p2r_ctx* ctx, uint64_t seed, p2r_mlp** out);
+int p2r_mlp_create(p2r_ctx* ctx, p2r_mlp** out, uint64_t seed);
 void p2r_mlp_destroy(p2r_mlp* mlp);
 int p2r_mlp_n_params(void);
 /* host_params: host array of p2r_mlp_n_params() floats; resets Adam; synchronises. */

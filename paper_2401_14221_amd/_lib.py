@@ -87,7 +87,7 @@ def library():
         L.p2r_ctx_reserve.argtypes = [vp, i32, i32]
         L.p2r_device_allocations.restype = C.c_ulonglong
         L.p2r_ctx_reserve_host.argtypes = [vp, i32, i32]
-        L.p2r_mlp_create.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+        L.p2r_mlp_create.argtypes = [vp, C.POINTER(vp), C.c_uint64]
         L.p2r_mlp_reserve.argtypes = [vp, i32]
         L.p2r_mlp_destroy.argtypes = [vp]
         L.p2r_mlp_destroy.restype = None
@@ -290,7 +290,7 @@ class Mlp:
         self.ctx = ctx
         self._h = vp()
         self._batch_cap = 0
-        _check(library().p2r_mlp_create(ctx._h, int(seed) & (2**64 - 1), C.byref(self._h)))
+        _check(library().p2r_mlp_create(ctx._h, C.byref(self._h), int(seed) & (2**64 - 1)))
         self.n_params = library().p2r_mlp_n_params()
         if params is not None:
             self.set_params(params)

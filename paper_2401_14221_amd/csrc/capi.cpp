@@ -843,7 +843,7 @@ static void mlp_init_params(uint64_t seed, std::vector<float>& w) {
     fill(o, (size_t)nh, nh, 0.1f);                                            // w3, b3 = 0
 }
 
-int p2r_mlp_create(p2r_ctx* ctx, uint64_t seed, p2r_mlp** out) {
+int p2r_mlp_create(p2r_ctx* ctx, p2r_mlp** out, uint64_t seed) {
     if (!ctx || !out) return fail(P2R_EINVAL, "NULL argument");
     *out = nullptr;
     DeviceGuard g(ctx->device);

@@ -93,6 +93,14 @@ def test_host_pipeline_edge_cases(ctx):
     m = p2r.Mlp(ctx)
     with pytest.raises(p2r.P2RError):
         ctx.propagate_update_host(0, 100, surf, trk, hits, mlp=m.handle.value)
+    # the sizing call's argument checks
+    for bad in ((-1, 0), (5000, 0), (20, -3)):
+        with pytest.raises(p2r.P2RError) as e:
+            ctx.reserve_host(*bad)
+        assert e.value.code == p2r.P2R_EINVAL
+    with pytest.raises(p2r.P2RError) as e:
+        m.reserve(0)
+    assert e.value.code == p2r.P2R_EINVAL
     # pageable host memory works too (copies serialise)
     r = ctx.propagate_update_host(1, 100, surf, trk.clone(), hits.clone(), chunk_tracks=64)
     torch.cuda.synchronize()
