@@ -688,144 +688,6 @@ __device__ __noinline__ uint32_t kalman_update_fp64(Fp64Io* io, float chi2_cut) 
     return 0;
 }
 
-// Update of state st (already propagated to the surface) with hit m, V.
-//   S = C'_pos + V;  w = S^-1 r;  chi2 = r . w;  K = C' H^T S^-1 (6x3);
-//   p+ = p' + C' H^T w;
-//   C+ = A C' A^T + K V K^T,  A = I - K H   (Joseph form).
-// The Joseph form is evaluated as written: in FP32 its dominant term K V K^T
-// carries no cancellation, while A C' A^T is second order in the (small)
-// rows of A along the measured directions, so the posterior keeps close to
-// FP32 relative accuracy even when the update shrinks C' by orders of
-// magnitude.  When the FP32 positive-definiteness test of S fails:
-// fp64_fallback 1 inverts S in FP64 and continues in FP32; 3 runs the whole
-// update in FP64 (kalman_update_fp64); 0 skips the update.  Mode 2 runs the
-// FP64 update for every surface (testing).
-// Returns 0, or ST_S_NOT_PD / ST_CHI2_CUT when the update is skipped;
-// ST_FP64_FALLBACK is OR-ed into *flags when an FP64 path ran.
-//
-// The FP32 arithmetic has no branch: a lane whose update is skipped (or was
-// done by the FP64 path) runs it with S^-1 and w set to zero, so that K = 0,
-// A = I and every FMA below returns its accumulator unchanged -- p and C
-// come out bit for bit as they went in.  Branching around it instead makes
-// the compiler copy the whole state into merge registers on every layer.
-template <typename T>
-__device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], const T V[6],
-                                                  const Params& P, T& chi2, uint32_t& flags) {
-    T* c = st.c;
-    T S[6] = {c[0] + V[0], c[1] + V[1], c[2] + V[2], c[3] + V[3], c[4] + V[4], c[5] + V[5]};
-    T Si[6];
-    constexpr bool F32 = sizeof(T) == sizeof(float);
-    const bool pd = inv3_spd<T>(S, Si, F32 ? T(PD_TAU32) : T(PD_TAU_F64_FIT));
-    uint32_t res = 0;
-    bool done = false;                    // the state was updated by the FP64 path
-    if constexpr (!F32) {
-        if (!pd) res = ST_S_NOT_PD;
-    } else if (P.fp64_fallback == 2 || !pd) {
-        if (!P.fp64_fallback) {
-            res = ST_S_NOT_PD;
-        } else {
-            flags |= ST_FP64_FALLBACK;
-            if (P.fp64_fallback != 1) {
-                // the out-of-line call works on a copy made here, so that the
-                // state itself never has its address taken and stays in registers
-                Fp64Io io;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) io.p[k] = (double)st.p[k] + (double)st.lo[k];
-#pragma unroll
-                for (int k = 0; k < 21; ++k) io.c[k] = st.c[k];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) io.m[k] = m[k];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) io.V[k] = V[k];
-                io.chi2 = (float)chi2;
-                res = kalman_update_fp64(&io, P.chi2_cut);
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    st.p[k] = (float)io.p[k];
-                    st.lo[k] = k == 3 ? 0.0f : (float)(io.p[k] - (double)st.p[k]);
-                }
-#pragma unroll
-                for (int k = 0; k < 21; ++k) st.c[k] = io.c[k];
-                chi2 = io.chi2;
-                done = true;
-            } else {
-                double Sd[6], Sid[6];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) Sd[k] = (double)c[k] + (double)V[k];
-                if (!inv3_spd<double>(Sd, Sid, PD_TAU64)) res = ST_S_NOT_PD;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) Si[k] = (T)Sid[k];
-            }
-        }
-    }
-    T r0 = residual_of(st, 0, m[0]), r1 = residual_of(st, 1, m[1]), r2 = residual_of(st, 2, m[2]);
-    T w0 = Si[0] * r0 + Si[1] * r1 + Si[3] * r2;
-    T w1 = Si[1] * r0 + Si[2] * r1 + Si[4] * r2;
-    T w2 = Si[3] * r0 + Si[4] * r1 + Si[5] * r2;
-    T c2 = r0 * w0 + r1 * w1 + r2 * w2;
-    if (res == 0 && !done && P.chi2_cut > 0.0f && c2 > T(P.chi2_cut)) res = ST_CHI2_CUT;
-    const bool apply = res == 0 && !done;
-    if (apply) chi2 = c2;
-    w0 = apply ? w0 : T(0.0);
-    w1 = apply ? w1 : T(0.0);
-    w2 = apply ? w2 : T(0.0);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) Si[k] = apply ? Si[k] : T(0.0);
-    // K = P S^-1 with P = C' H^T (rows c(i,0..2)); KV = K V
-    T K[6][3], KV[6][3];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        T p0 = c[I21(i, 0)], p1 = c[I21(i, 1)], p2 = c[I21(i, 2)];
-        K[i][0] = p0 * Si[0] + p1 * Si[1] + p2 * Si[3];
-        K[i][1] = p0 * Si[1] + p1 * Si[2] + p2 * Si[4];
-        K[i][2] = p0 * Si[3] + p1 * Si[4] + p2 * Si[5];
-        KV[i][0] = K[i][0] * V[0] + K[i][1] * V[1] + K[i][2] * V[3];
-        KV[i][1] = K[i][0] * V[1] + K[i][1] * V[2] + K[i][2] * V[4];
-        KV[i][2] = K[i][0] * V[3] + K[i][1] * V[4] + K[i][2] * V[5];
-        const T dp = fma_(p0, w0, fma_(p1, w1, p2 * w2));
-        if (i == 3) st.p[i] += dp;
-        else add_to(st, i, dp);
-    }
-    // M = A C' (entries (i, l) with l <= i, and (i, j) with j < 3)
-    auto Mv = [&](int i, int l) -> T {
-        T a = c[I21(i, l)];
-        a = fma_(-K[i][0], c[I21(0, l)], a);
-        a = fma_(-K[i][1], c[I21(1, l)], a);
-        a = fma_(-K[i][2], c[I21(2, l)], a);
-        return a;
-    };
-    T M[6][6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int l = 0; l < 6; ++l)
-            if (l <= i || l < 3) M[i][l] = Mv(i, l);
-    // C+ = M A^T + K V K^T = M + (K V - M H^T) K^T (lower triangle).  At
-    // the optimal gain M H^T = K V exactly, so D = K V - M H^T holds only
-    // the rounding residual that the Joseph form exists to absorb; forming
-    // it first subtracts the two nearly equal terms exactly (Sterbenz)
-    // instead of carrying both through each element's sum.
-    T D[6][3];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) D[i][j] = KV[i][j] - M[i][j];
-    T n[21];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int l = 0; l <= i; ++l) {
-            T a = M[i][l];
-            a = fma_(D[i][0], K[l][0], a);
-            a = fma_(D[i][1], K[l][1], a);
-            a = fma_(D[i][2], K[l][2], a);
-            n[I21(i, l)] = a;
-        }
-#pragma unroll
-    for (int k = 0; k < 21; ++k) c[k] = n[k];
-    return res;
-}
-
 // Update on a cylinder in the hit's (r-phi, z) frame.  With (c, s) the
 // hit's direction in the transverse plane only the two coordinates along the
 // surface are measured: u = -s x + c y (u_hit = 0) and z, i.e.
@@ -833,8 +695,9 @@ __device__ __forceinline__ uint32_t kalman_update(StateT<T>& st, const T m[3], c
 //   R = [[-s, c, 0], [0, 0, 1]];
 // then S = H C' H^T + V2 (2x2), K = C' H^T S^-1 (6x2), p+ = p' + K r,
 // chi2 = r^T S^-1 r, and the Joseph covariance, evaluated as
-// C+ = M + (K V2 - M H^T) K^T with M = A C' = C' - K (C' H^T)^T, as in the
-// 3D update.  Same skip rules, fallback modes and zero-gain trick as there.
+// C+ = M + (K V2 - M H^T) K^T with M = A C' = C' - K (C' H^T)^T, as in
+// kalman_update_surf.  Same skip rules, fallback modes and zero-gain trick
+// as there.
 template <typename T>
 __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3], const T V[6],
                                                      const Params& P, T& chi2, uint32_t& flags);
@@ -998,9 +861,27 @@ __device__ __forceinline__ uint32_t kalman_update_2d(StateT<T>& st, const T m[3]
 // corrected for the normal component, at about two thirds of the cost of
 // the 3x3 algebra.  KIND 0: cylinder, 1: plane, 2: chosen per lane by
 // `kind` (kernels whose lanes meet both in one row share one update).
-// Skip rules, fallback modes and the zero-gain trick are those of
-// kalman_update; the FP32 PD test is on S^ (and Vnn > 0), and the FP64
-// fallback runs the 3x3 update in FP64.
+//
+// The Joseph form, C+ = A C' A^T + K V^ K^T with A = I - K H, is evaluated
+// as M + (K V^ - M H^T) K^T, M = A C' = C' - K P^T: at the optimal gain
+// M H^T = K V^ exactly, so K V^ - M H^T holds only the rounding residual the
+// Joseph form exists to absorb, and forming it first subtracts the two
+// nearly equal terms exactly instead of carrying both through every element.
+// The posterior keeps close to FP32 relative accuracy even when the update
+// shrinks C' by orders of magnitude.
+//
+// When the FP32 positive-definiteness test (the pivots of S^, and V_nn > 0)
+// fails: fp64_fallback 3 runs the whole 3x3 update in FP64
+// (kalman_update_fp64), 1 inverts S^ in FP64 and continues in FP32, 0 skips
+// the update; mode 2 runs the FP64 update for every surface (testing).
+// Returns 0, or ST_S_NOT_PD / ST_CHI2_CUT when the update is skipped;
+// ST_FP64_FALLBACK is OR-ed into *flags when an FP64 path ran.
+//
+// The FP32 arithmetic has no branch: a lane whose update is skipped (or was
+// done by the FP64 path) runs it with S^-1 and w set to zero, so that K = 0
+// and every FMA below returns its accumulator unchanged -- p and C come out
+// bit for bit as they went in.  Branching around it instead makes the
+// compiler copy the whole state into merge registers on every layer.
 template <typename T, int KIND>
 __device__ __forceinline__ uint32_t kalman_update_surf(StateT<T>& st, const T m[3], const T V[6],
                                                        const Params& P, T& chi2, uint32_t& flags,
