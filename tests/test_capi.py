@@ -55,3 +55,18 @@ def test_variant_listing_is_host_only():
     assert "p2r_w64_e0_u1" in names and all(n.startswith("p2r_w") for n in names)
     assert p2r.variant_names(1) and all(n.startswith("p2z_") for n in p2r.variant_names(1))
     assert p2r.variant_names(2) and p2r.variant_names(7) == []
+
+
+def test_sizing_and_noalloc_calls_reject_null_handles():
+    """The sizing calls and the allocation-free fit check their handles on
+    the host, before any HIP call."""
+    lib = p2r.library()
+    assert lib.p2r_ctx_reserve(None, 10, 5) == p2r.P2R_EINVAL
+    assert lib.p2r_ctx_reserve_host(None, 20, 0) == p2r.P2R_EINVAL
+    assert lib.p2r_mlp_reserve(None, 64) == p2r.P2R_EINVAL
+    out = C.c_void_p()
+    assert lib.p2r_mlp_create(None, C.byref(out), 7) == p2r.P2R_EINVAL
+    o = _lib.default_opts()
+    rc = lib.fit_tracks_batched_noalloc(None, C.byref(o), 10, 100, 25, *([None] * 13))
+    assert rc == p2r.P2R_EINVAL
+    assert p2r.device_allocations() == 0
