@@ -63,8 +63,10 @@ def report(name, g, r, final_surface, dump=None):
     print(f"== {name}: {n} tracks, {len(f['excluded'])} excluded", flush=True)
     bad = {k: f[k] for k in ("status", "par", "chi2", "cov")}
     print("  tracks failing: " + ", ".join(f"{k} {len(v)}" for k, v in bad.items()))
+    keep = np.ones(n, bool)
+    keep[f["excluded"]] = False
     for k in ("par", "chi2", "cov"):
-        rr, raw, w = f[k + "_ratio"], f[k + "_raw"], f["widen_" + k]
+        rr, raw, w = f[k + "_ratio"], f[k + "_raw"], np.where(keep, f["widen_" + k], 1.0)
         print(f"  {k}: largest error / bound {rr.max():.3f}; 99.99% {np.quantile(rr, 0.9999):.3f}; "
               f"99.9% {np.quantile(rr, 0.999):.3f}; error / base bound above 1 in {int((raw > 1).sum())} tracks; "
               f"bound widened in {int((w > 1).sum())} tracks (widest x{w.max():.3g})")

@@ -156,3 +156,21 @@ def test_decisions_of_an_fp32_run_exclude_the_track(fit):
     g["par"][t, 0] += 1.0
     rep = compare(g, r2, ctx="f32 decision", max_excluded_frac=0.01)
     assert rep["excluded"] == 1
+
+
+def test_widening_is_capped_and_beyond_it_the_track_is_excluded(fit):
+    from .parity import PAR_F, PAR_TOL, SENS_CAP, SENS_FACTOR
+    d, r = fit
+    t, col = 12, 0
+    r2 = _with_sensitivity(r, t, col, 2 * SENS_CAP / SENS_FACTOR)   # would widen to 2 SENS_CAP
+    g = _as_gpu(r)
+    g["par"][t, col] += 10 * SENS_CAP * PAR_TOL * max(abs(r["par"][t, col]), PAR_F[col])
+    rep = compare(g, r2, ctx="ill-posed")          # one exclusion is always allowed
+    assert rep["excluded"] == 1 and rep["widest"]["par"] <= SENS_CAP
+    # a second ill-posed track exceeds the 1e-4 allowance of 200 tracks
+    r3 = dict(r2)
+    s = {k: v.copy() for k, v in r2["f32_runs"][0].items()}
+    s["par"][t + 5, col] += 2 * SENS_CAP / SENS_FACTOR * PAR_TOL * max(abs(r["par"][t + 5, col]), PAR_F[col])
+    r3["f32_runs"] = [s]
+    with pytest.raises(AssertionError, match="excluded"):
+        compare(g, r3, ctx="two ill-posed tracks")
