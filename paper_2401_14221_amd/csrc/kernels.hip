@@ -40,6 +40,14 @@ __device__ __forceinline__ void count_evals(unsigned long long* evals, int iters
     if (__lane_id() == 0) atomicAdd(evals, v);
 }
 
+// The next layer's surface value, loaded with the next layer's hit.  The
+// table is read through a vector load (the kernel's stores could alias it as
+// far as the compiler knows), and vector loads land in order: one issued
+// after the hit prefetch and used in the current layer would make the layer
+// wait for the whole prefetch.  Loaded a layer ahead, it is needed only when
+// the prefetch is.
+__device__ __forceinline__ float next_surface(const float* surf, int ly) { return surf[ly]; }
+
 // p2r: hits [block][layer][9][W].  LEARNED: the path-length MLP proposes the
 // start of every helix-to-cylinder solve; the whole wave evaluates it on the
 // matrix cores, so every lane stays in the layer loop (lanes past n shadow
@@ -75,16 +83,19 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
         float hm[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
+        // the layer radius travels with the prefetched hit (see next_surface)
+        float rn = a.L > 0 ? a.surf[0] : 0.0f;
 #pragma unroll UNROLL
         for (int ly = 0; ly < a.L; ++ly) {
             const T m[3] = {hm[0], hm[1], hm[2]};
             const T V[6] = {hm[3], hm[4], hm[5], hm[6], hm[7], hm[8]};
+            const T R = rn;
             if (ly + 1 < a.L) {
                 const float* hn = hb + (size_t)(ly + 1) * (9 * W);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hm[k] = hn[k * W];
+                rn = next_surface(a.surf, ly + 1);
             }
-            const T R = a.surf[ly];
             T s_start = NAN;
             if (LEARNED) {
                 float sphi, cphi;
@@ -141,17 +152,20 @@ __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
         float hm[9];                      // (no layers: see p2r_body)
 #pragma unroll
         for (int k = 0; k < 9; ++k) hm[k] = hb[k * W];
+        float zn = a.L > 0 ? a.surf[0] : 0.0f;
 #pragma unroll UNROLL
         for (int ly = 0; ly < a.L; ++ly) {
             const T m[3] = {hm[0], hm[1], hm[2]};
             const T V[6] = {hm[3], hm[4], hm[5], hm[6], hm[7], hm[8]};
+            const T Z = zn;
             if (ly + 1 < a.L) {
                 const float* hn = hb + (size_t)(ly + 1) * lstride;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hm[k] = hn[k * W];
+                zn = next_surface(a.surf, ly + 1);
             }
             T c2 = 0;
-            StepOut o = step_plane<T>(st, zsign * T(a.surf[ly]), m, V, P, c2);
+            StepOut o = step_plane<T>(st, zsign * Z, m, V, P, c2);
             flags |= o.flags;
             if (o.updated) { ++nused; chi2 += c2; }
         }

@@ -257,6 +257,17 @@ __device__ __forceinline__ int opaque_lane(int lane) {
     return lane;
 }
 
+// Wait until every vector memory load this wave issued has landed.  A slot
+// past a track's run is loaded but never stored, and the compiler's wait
+// tracking keeps such a load pending: a register it wrote and the fit later
+// reuses would then need a wait inside the fit loop, which the in-order load
+// counter turns into a wait for the whole prefetch issued after it.  Taken
+// once per chunk, after the stores, where every load has landed anyway.
+__device__ __forceinline__ void loads_landed() {
+    // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima (7, 15)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
 // Element i of an array at a 32-bit byte offset from its base (the call
 // checks that every CSR array stays below 4 GiB), so that each load needs one
 // offset register rather than a 64-bit address.
@@ -371,6 +382,7 @@ __device__ __forceinline__ void fit_block(const RaggedLaunch& a, const Params& P
             surf_load<CB>(a, S.run, lane, k0, RS);
             surf_store<C, CB>(S, lane, k0, RS);
         }
+        loads_landed();
         __syncthreads();
         const int k1 = k0 + C;
         if (PREFETCH && k1 < rows) hit_load<C>(a, S.run, lane, k1, RH);
