@@ -16,6 +16,11 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in the VGPRs: with the AGPR form the learned
+    # fit kernel held 232 VGPRs + 48 AGPRs of the unified 512 (one wave per
+    # SIMD) and copied every accumulator out of the AGPRs; in VGPR form it
+    # needs 196 (two waves per SIMD) and no copies
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 SOURCES = ["kernels.hip", "ragged.hip", "mlp.hip", "capi.cpp"]

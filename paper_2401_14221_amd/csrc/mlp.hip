@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(64) mlp_grads_kernel(const MlpWeights* __restr
                 const float g = A.z2[mb][nb][j] > 0.0f ? dyb[nb] * W.w3[o] : 0.0f;
                 dz2[mb][nb][j] = g;
                 T.dz2[o][nb * 32 + r32] = g;
-                T.h1[o][nb * 32 + r32] = fmaxf(A.z1[mb][nb][j], 0.0f);
+                T.h1[o][nb * 32 + r32] = relu(A.z1[mb][nb][j]);
             }
     // dh1 = W2^T dz2 on the matrix cores; K order = dz2's register order
     floatx16 dz1[2][2];
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(64) mlp_grads_kernel(const MlpWeights* __restr
         for (int j = 0; j < 16; ++j) {
             float v = 0.0f;
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) v = fmaf(dyb[nb], fmaxf(A.z2[mb][nb][j], 0.0f), v);
+            for (int nb = 0; nb < 2; ++nb) v = fmaf(dyb[nb], relu(A.z2[mb][nb][j]), v);
             // reduce over the 32 lanes of this half (same hidden unit)
 #pragma unroll
             for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);

@@ -29,10 +29,17 @@ __device__ __forceinline__ floatx16 bias_init(const float* b, int base, int hi) 
     return c;
 }
 
+// max(x, 0) as one integer max on the bit pattern: a float with its sign bit
+// set is a negative integer, so it becomes +0 and every other value passes
+// unchanged.  (fmaxf costs two instructions here: the compiler first
+// quiets a possible signalling NaN, which the pre-activations, sums of
+// finite products, never are.)
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 __device__ __forceinline__ bf16x8 relu_bf16(const floatx16& a, int from) {
     bf16x8 v;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = (__bf16)fmaxf(a[from + k], 0.0f);
+    for (int k = 0; k < 8; ++k) v[k] = (__bf16)relu(a[from + k]);
     return v;
 }
 
@@ -82,7 +89,7 @@ __device__ __forceinline__ float mlp_eval(const MlpWeights& W, const float feat[
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int j = 0; j < 16; ++j) s = fmaf(W.w3[mb * 32 + blk_row(j, hi)], fmaxf(z2[mb][nb][j], 0.0f), s);
+            for (int j = 0; j < 16; ++j) s = fmaf(W.w3[mb * 32 + blk_row(j, hi)], relu(z2[mb][nb][j]), s);
         part[nb] = s + __shfl_xor(s, 32);
     }
     if (keep) {
@@ -129,7 +136,7 @@ __device__ __forceinline__ float mlp_infer(const MlpWeights& W, const float feat
             for (int c = 0; c < 4; ++c)
                 acc = mfma32(load_bf16x8(&W.w2[mb][c][r32][8 * hi]), h1[c >> 1][nb][c & 1], acc);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) part[nb] = fmaf(W.w3[mb * 32 + blk_row(j, hi)], fmaxf(acc[j], 0.0f), part[nb]);
+            for (int j = 0; j < 16; ++j) part[nb] = fmaf(W.w3[mb * 32 + blk_row(j, hi)], relu(acc[j]), part[nb]);
         }
     }
     const float s0 = part[0] + __shfl_xor(part[0], 32);

@@ -296,7 +296,7 @@ def test_autotune_picks_a_variant(ctx, tmp_path):
     with pytest.raises(p2r.P2RError):
         c3.set_variant(0, "no_such_kernel")
     with pytest.raises(p2r.P2RError):
-        c3.set_variant(0, "p2r_mlp_w64_e0_u1")     # learned kernels are chosen by opts.mlp
+        c3.set_variant(0, "p2r_mlp_w64_e3_u1")     # learned kernels are chosen by opts.mlp
     assert c3.variant_name(0) == "p2r_w128_e4_u1"
     c3.close()
 
