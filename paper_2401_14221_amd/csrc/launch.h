@@ -80,14 +80,19 @@ struct RaggedLaunch {
     int32_t* work;             // [1] work-queue counter
     int32_t* perm;             // [n] sorted position -> track index
     int32_t* keys;             // [n] sort key of every track
-    int64_t* run;              // [n] sorted position -> the track's first hit | surface count << 56
+    int64_t* run;              // [n] sorted position -> the track's first hit | surface count << 48
                                //     (RAG_RUN_SHIFT), or -1 for a track in the invalid bucket
     int32_t nkeys;
     int32_t nb;                // blocks of RAG_W sorted tracks
     int32_t grid;              // workgroups of the persistent variant (one wave each)
 };
 
-constexpr int RAG_RUN_SHIFT = 56;
+// The first hit takes the low 48 bits (n_hits < 2^32), the surface count
+// (0..255) the bits above, so that every valid run is non-negative and -1
+// stays free for the invalid bucket.  (A shift of 56 put counts of 128 and
+// more into the sign bit: such tracks, and every track of their block, were
+// skipped.)
+constexpr int RAG_RUN_SHIFT = 48;
 int ragged_nkeys(int lmax);
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s);
 

@@ -88,6 +88,33 @@ def test_ragged_fit_variants(variant):
         c.close()
 
 
+def test_ragged_long_tracks_every_variant():
+    """Tracks of 100..255 surfaces (140 cylinders and 140 disks on each side;
+    255 is the largest surface count the call accepts): each wave stages
+    many hit chunks and reloads its surface types and values many times.
+    Every compiled variant against the oracle.  (Surface counts of 128 and
+    more once fell into the sign bit of the sorted run encoding, and their
+    whole block was skipped.)"""
+    ex = dict(ev.RAGGED.extra)
+    ex.update(barrels=np.linspace(2.5, 110.0, 140).astype(np.float32),
+              disks=np.linspace(30.0, 270.0, 140).astype(np.float32), lmin=100, lmax=255)
+    d = ev.make_ragged_event(ev.RAGGED.with_(seed=71, extra=ex), n_tracks=600)
+    L = np.diff(d["offsets"])
+    assert L.min() >= 100 and L.max() == 255 and (L >= 128).sum() > 300
+    r = oracle.fit_ragged(d, chi2_cut=CUT)
+    fs = final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"])
+    u = upload(d)
+    for variant in p2r.variant_names(2):
+        c = p2r.Context(0)
+        try:
+            c.set_variant(2, variant)
+            g = run(c, u, int(d["offsets"][-1]), lmax=255, stream=torch.cuda.Stream(), use_graph=1)
+            assert np.all(((g["status"] >> 8) & 0xFF) <= L)
+            print(variant, compare(g, r, ctx=f"long tracks, {variant}", final_surface=fs), flush=True)
+        finally:
+            c.close()
+
+
 def test_ragged_graph_replays_match_eager(ctx):
     """Replays of the captured graph, with unrelated eager work between them, equal the eager launch bit for bit."""
     d = ev.make_ragged_event(ev.RAGGED.with_(seed=55), n_tracks=5000)
