@@ -40,7 +40,8 @@
  *    Everything is released by the matching destroy.
  *
  * Status word per track: bits 0..7 flags, bits 8..15 the number of surfaces
- * whose update was applied, bit 31 set when the track was processed.
+ * whose update was applied (saturating at 255), bit 31 set when the track
+ * was processed.
  */
 #ifndef P2R_H
 #define P2R_H

@@ -126,7 +126,7 @@ __device__ __forceinline__ void p2r_body(const FitLaunch& a, const Params& P, Ml
     finalise(st);
     store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
     a.chi2[gid] = (float)chi2;
-    a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
+    a.status[gid] = flags | ST_DONE | nused_field(nused);
 }
 
 // p2z: W = 64, hits [layer][block][9][64]; disk sign from the input theta
@@ -173,7 +173,7 @@ __device__ __forceinline__ void p2z_body(const FitLaunch& a, const Params& P) {
     finalise(st);
     store_track(a.trk_out + (size_t)b * (28 * W) + l, W, st);
     a.chi2[gid] = (float)chi2;
-    a.status[gid] = flags | ST_DONE | ((uint32_t)nused << NUSED_SHIFT);
+    a.status[gid] = flags | ST_DONE | nused_field(nused);
 }
 
 #define P2R_KERNEL(W, WPE, U)                                                              \

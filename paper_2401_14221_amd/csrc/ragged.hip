@@ -425,7 +425,7 @@ __device__ __forceinline__ void fit_block(const RaggedLaunch& a, const Params& P
 #pragma unroll
     for (int f = 0; f < 21; ++f) a.cov_out[(size_t)t * 21 + f] = (float)st.c[f];
     a.chi2[t] = (float)chi2;
-    a.status[t] = flags | ST_DONE | ((uint32_t)(nused > 255 ? 255 : nused) << NUSED_SHIFT);
+    a.status[t] = flags | ST_DONE | nused_field(nused);
 }
 
 // One workgroup (one wave) per block: the dispatcher hands the blocks out in

@@ -31,6 +31,10 @@ enum : uint32_t {
     ST_DONE = 1u << 31,
 };
 constexpr int NUSED_SHIFT = 8;
+// status bits 8..15: the number of applied updates, saturating at 255
+__host__ __device__ __forceinline__ uint32_t nused_field(int nused) {
+    return (uint32_t)(nused > 255 ? 255 : nused) << NUSED_SHIFT;
+}
 
 // Relative pivot thresholds of the positive-definiteness test of S (a
 // pivot d_k must exceed tau * S_kk).  FP32: below 1e-3 the FP32 inverse

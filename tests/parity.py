@@ -113,10 +113,11 @@ def final_surface_of(par, offsets, surf_type, surf_val) -> np.ndarray:
 
 def _flags(res, with_nused: bool) -> np.ndarray:
     """Status words as int64, FP64_FALLBACK cleared; with_nused: the oracle's
-    separate update count folded into bits 8..15 like the GPU's."""
+    separate update count folded into bits 8..15 like the GPU's (saturating
+    at 255, as the status word's field does)."""
     s = np.asarray(res["status"]).astype(np.int64) & 0xFFFFFFFF
     if with_nused:
-        s = s | (np.asarray(res["nused"]).astype(np.int64) << 8)
+        s = s | (np.minimum(np.asarray(res["nused"]).astype(np.int64), 255) << 8)
     return s & ~np.int64(ST_FP64_FALLBACK)
 
 

@@ -335,6 +335,21 @@ def test_every_plain_variant_matches_oracle():
             c.close()
 
 
+def test_more_than_255_layers(ctx):
+    """300 layers: the applied-update count in the status word saturates at
+    255 (the oracle's exact count, 300 on most tracks, is compared through
+    the same saturating field), and the fit itself runs through every layer."""
+    d = ev.make_barrel_event(ev.P2R_PARITY.with_(surfaces=np.linspace(2.5, 110.0, 300).astype(np.float32),
+                                                 seed=77), n_tracks=512)
+    r = oracle.fit_event(d, "barrel")
+    assert (r["nused"] > 255).sum() > 400
+    for W in (64, 256):
+        g = run_p2r(ctx, d, W)
+        nused = (g["status"] >> 8) & 0xFF
+        assert np.array_equal(nused, np.minimum(r["nused"], 255))
+        print(f"300 layers W={W}", compare(g, r, ctx=f"300 layers W={W}"), flush=True)
+
+
 def test_zero_layers_pass_tracks_through(ctx):
     """n_layers = 0 with no hit or layer buffer at all: every track comes back
     unchanged, with chi2 0 and no surface used (nothing is read from the
