@@ -180,6 +180,33 @@ def test_ragged_edge_cases(ctx):
     assert empty[0].numel() == 0
 
 
+def test_ragged_negative_count_is_bad_input(ctx):
+    """offsets[21] < offsets[20]: track 20's count is negative, so it is
+    BAD_INPUT and comes back unchanged; track 21's run then starts 3 hits
+    earlier (CSR runs may overlap) and is fitted over it like any other."""
+    d = ev.make_ragged_event(ev.RAGGED.with_(seed=23), n_tracks=300)
+    off = d["offsets"].copy()
+    off[21] = off[20] - 3
+    e = dict(d, offsets=off)
+    g = run(ctx, upload(e), int(off[-1]))
+    assert g["status"][20] & p2r.ST_BAD_INPUT and g["status"][20] & p2r.ST_DONE
+    assert np.array_equal(g["par"][20], d["par"][20].astype(np.float32))
+    assert np.array_equal(g["cov"][20], d["cov"][20].astype(np.float32))
+    # every other track against the oracle (which knows no surface-count limit)
+    keep = np.setdiff1d(np.arange(300), [20])
+
+    def take(x):
+        if isinstance(x, dict):
+            return {k: take(v) for k, v in x.items()}
+        if isinstance(x, list):
+            return [take(v) for v in x]
+        return np.asarray(x)[keep]
+
+    r = oracle.fit_ragged(e, chi2_cut=CUT)
+    # (the final-surface kind only feeds a reported figure; these runs overlap)
+    compare(take(g), take(r), ctx="negative count", final_surface="cylinder")
+
+
 def test_ragged_full_size_sampled(ctx):
     """1,000,000 tracks with 5..25 mixed surfaces in one graph launch; every track processed exactly once."""
     d = ev.make_ragged_event(ev.RAGGED)
