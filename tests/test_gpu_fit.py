@@ -336,12 +336,16 @@ def test_every_plain_variant_matches_oracle():
 
 
 @pytest.mark.parametrize("case", ["barrel low pT", "barrel high pT", "disk low pT", "disk high pT",
-                                  "barrel layers reversed", "disks reversed"])
+                                  "barrel layers reversed", "disks reversed", "barrel B = 0", "disk B = 0"])
 def test_momentum_extremes_and_layer_order(ctx, case):
     """Loopers (pT 0.2..0.6 GeV: outer layers out of reach, hits missing where
     the particle never got), nearly straight tracks (pT 0.5..5 TeV, |omega s|
-    ~ 1e-6, where the sinc forms must not cancel), and layers given outside
-    in (every surface after the first lies behind the track: NO_CROSSING).
+    ~ 1e-6, where the sinc forms must not cancel), layers given outside in
+    (every surface after the first lies behind the track: NO_CROSSING), and
+    fits with no field (omega = 0 exactly: straight-line crossings and no
+    division by the curvature anywhere; the hits still curve, so chi2 is
+    large, which the comparison does not mind).
+
     Near-straight tracks barely measure their curvature (the sagitta over a
     metre is below the hit resolution), so 1/pT is ill-conditioned against a
     relative bound: the oracle's own FP32 runs miss its exact 1/pT by up to
@@ -356,8 +360,9 @@ def test_momentum_extremes_and_layer_order(ctx, case):
     d = make(base.with_(pt=pt, seed=81 + len(case)), n_tracks=1024)
     if "reversed" in case:
         d = dict(d, surf=d["surf"][::-1].copy(), hits=d["hits"][:, ::-1].copy(), hitcov=d["hitcov"][:, ::-1].copy())
-    r = oracle.fit_event(d, kind)
-    g = run_p2r(ctx, d, 64) if kind == "barrel" else run_p2z(ctx, d)
+    bz = 0.0 if "B = 0" in case else 3.8
+    r = oracle.fit_event(d, kind, bz=bz)
+    g = run_p2r(ctx, d, 64, bz_tesla=bz) if kind == "barrel" else run_p2z(ctx, d, bz_tesla=bz)
     cap = 1e5 if ("high" in case or "reversed" in case) else None
     kw = {} if cap is None else {"sens_cap": cap}
     fs = "cylinder" if kind == "barrel" else "plane"
