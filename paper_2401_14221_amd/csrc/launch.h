@@ -89,9 +89,8 @@ struct RaggedLaunch {
 
 // The first hit takes the low 48 bits (n_hits < 2^32), the surface count
 // (0..255) the bits above, so that every valid run is non-negative and -1
-// stays free for the invalid bucket.  (A shift of 56 put counts of 128 and
-// more into the sign bit: such tracks, and every track of their block, were
-// skipped.)
+// stays free for the invalid bucket (with the count at bit 56, counts of 128
+// and more would set the sign bit and read as invalid).
 constexpr int RAG_RUN_SHIFT = 48;
 int ragged_nkeys(int lmax);
 hipError_t launch_ragged(const Variant& v, const RaggedLaunch& a, const Params& P, hipStream_t s);
