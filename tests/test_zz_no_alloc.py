@@ -31,10 +31,10 @@ def _outputs(n):
             torch.full((n,), np.nan, device="cuda"), torch.zeros(n, dtype=torch.int32, device="cuda")]
 
 
-def _call(fn, ctx, d, ins, outs, stream):
+def _call(fn, ctx, d, ins, outs, stream, max_surfaces=25):
     o = _lib.default_opts(chi2_cut=CUT, use_graph=0)
     ptr = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
-    return fn(ctx._h, C.byref(o), d["par"].shape[0], int(d["offsets"][-1]), 25, *[ptr(t) for t in ins],
+    return fn(ctx._h, C.byref(o), d["par"].shape[0], int(d["offsets"][-1]), max_surfaces, *[ptr(t) for t in ins],
               *[ptr(t) for t in outs], C.c_void_p(stream.cuda_stream))
 
 
@@ -83,5 +83,35 @@ def test_noalloc_refuses_more_tracks_than_its_scratch_holds():
                                             p, p, None)
         assert rc == p2r.P2R_ENOSPACE
         assert b"at most" in lib.p2r_last_error()
+    finally:
+        ctx.close()
+
+
+def test_noalloc_at_its_limits():
+    """P2R_NOALLOC_MAX_TRACKS tracks with max_surfaces = 255 (the largest
+    sort-key histogram): every region of the scratch array at its full size,
+    with the same results as fit_tracks_batched."""
+    lib = _lib.library()
+    ctx = p2r.Context(0)
+    s = torch.cuda.Stream()
+    try:
+        n = int(p2r.P2R_NOALLOC_MAX_TRACKS)
+        d = ev.make_ragged_event(ev.RAGGED.with_(seed=43), n_tracks=n)
+        ins = _upload(d)
+        ref_out = _outputs(n)
+        ctx.reserve(n, 255)
+        assert _call(lib.fit_tracks_batched, ctx, d, ins, ref_out, s, max_surfaces=255) == 0
+        torch.cuda.synchronize()
+        na_out = _outputs(n)
+        before = p2r.device_allocations()
+        print(f"noalloc call n={n} max_surfaces=255", flush=True)
+        assert _call(lib.fit_tracks_batched_noalloc, ctx, d, ins, na_out, s, max_surfaces=255) == 0, \
+            lib.p2r_last_error()
+        torch.cuda.synchronize()
+        assert p2r.device_allocations() == before
+        g, ref = _host(na_out), _host(ref_out)
+        for k in ("par", "cov", "chi2", "status"):
+            assert np.array_equal(g[k], ref[k], equal_nan=True), k
+        assert np.all(g["status"] & p2r.ST_DONE)
     finally:
         ctx.close()
