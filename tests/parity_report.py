@@ -1,6 +1,7 @@
-"""Full-size parity report: every track of the p2r, p2z and ragged benchmark
-workloads fitted on the GPU and by the FP64 oracle, compared element by
-element.  Prints, per workload, the largest error of every output, how many
+"""Full-size parity report: every track of the p2r, p2z, ragged and
+learned-start benchmark workloads fitted on the GPU and by the FP64 oracle,
+compared element by element.  Prints, per workload, the largest error of
+every output, how many
 covariance elements pass under each branch of the rule in tests/parity.py,
 how many tracks had a bound widened by the oracle's measured FP32
 sensitivity, and how many end at a shallow incidence.
@@ -17,17 +18,22 @@ import time
 import numpy as np
 
 
-def _gpu_p2r(p2r, ctx, d, W):
+def _gpu_p2r(p2r, ctx, d, W, mlp=None):
     import torch
     n = d["par"].shape[0]
     trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device="cuda")
     hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device="cuda")
     radii = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
-    out, chi2, st = ctx.p2r_propagate_update(n, radii, trk, hits, width=W)
+    opts = p2r._lib.default_opts(width=W)
+    if mlp is not None:
+        opts.mlp = mlp.handle.value
+    out, chi2, st = ctx.p2r_propagate_update(n, radii, trk, hits, opts=opts)
     torch.cuda.synchronize()
     par, cov, _ = p2r.unpack_tracks(out, n)
-    return dict(par=par.cpu().numpy(), cov=cov.cpu().numpy(), chi2=chi2.cpu().numpy(),
-                status=st.cpu().numpy().view(np.uint32))
+    st = st.cpu().numpy().view(np.uint32)
+    if mlp is not None:
+        st = st & ~np.uint32(p2r.ST_ML_REJECTED)      # a GPU-only bit: the proposal was not used
+    return dict(par=par.cpu().numpy(), cov=cov.cpu().numpy(), chi2=chi2.cpu().numpy(), status=st)
 
 
 def _gpu_p2z(p2r, ctx, d):
@@ -135,6 +141,16 @@ def main():
     r = oracle.fit_ragged(d, chi2_cut=cut, nthreads=16)
     fs = final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"])
     report(f"ragged {ev.RAGGED.name} (chi2 cut {cut:g})", g, r, fs, dump=_dump("ragged"))
+    print(f"  ({time.time() - t:.0f} s)", flush=True)
+    del d, g, r
+    from paper_2401_14221_amd import learned
+    t = time.time()
+    mlp = p2r.Mlp(ctx)
+    mlp.load(learned.DEFAULT_CKPT)
+    d = ev.make_barrel_event(ev.LEARNED_EVAL)
+    g = _gpu_p2r(p2r, ctx, d, W, mlp=mlp)
+    r = oracle.fit_event(d, "barrel", nthreads=16)
+    report(f"p2r learned start {ev.LEARNED_EVAL.name} (W={W})", g, r, "cylinder", dump=_dump("learned"))
     print(f"  ({time.time() - t:.0f} s)", flush=True)
     ctx.close()
 
