@@ -1,14 +1,15 @@
-"""Full-size parity report: every track of the p2r, p2z, ragged and
-learned-start benchmark workloads fitted on the GPU and by the FP64 oracle,
-compared element by element.  Prints, per workload, the largest error of
-every output, how many
-covariance elements pass under each branch of the rule in tests/parity.py,
-how many tracks had a bound widened by the oracle's measured FP32
-sensitivity, and how many end at a shallow incidence.
+"""Full-size parity report: every track of the p2r, p2z, ragged,
+learned-start and hit-frame-update benchmark workloads fitted on the GPU and
+by the FP64 oracle, compared element by element.  Prints, per workload, the
+largest error of every output, how many covariance elements pass under each
+branch of the rule in tests/parity.py, how many tracks had a bound widened
+by the oracle's measured FP32 sensitivity, and how many end at a shallow
+incidence.
 
-Needs a GPU and the built libraries:  python -m tests.parity_report [--dump DIR]
-(--dump writes the GPU and oracle outputs of the tracks that fail a check
-to DIR/parity_fail_<workload>.npz.)
+Needs a GPU and the built libraries:
+  python -m tests.parity_report [p2r p2z ragged learned p2r_2d] [--dump DIR]
+(workload names select some of them, default all; --dump writes the GPU and
+oracle outputs of the tracks that fail a check to DIR/parity_fail_<name>.npz.)
 """
 from __future__ import annotations
 
@@ -18,13 +19,13 @@ import time
 import numpy as np
 
 
-def _gpu_p2r(p2r, ctx, d, W, mlp=None):
+def _gpu_p2r(p2r, ctx, d, W, mlp=None, update_2d=0):
     import torch
     n = d["par"].shape[0]
     trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device="cuda")
     hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device="cuda")
     radii = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
-    opts = p2r._lib.default_opts(width=W)
+    opts = p2r._lib.default_opts(width=W, update_2d=update_2d)
     if mlp is not None:
         opts.mlp = mlp.handle.value
     out, chi2, st = ctx.p2r_propagate_update(n, radii, trk, hits, opts=opts)
@@ -115,45 +116,48 @@ def main():
 
     import oracle
     import paper_2401_14221_amd as p2r
+    from paper_2401_14221_amd import learned
     from synth import events as ev
     from tests.parity import final_surface_of
 
+    names = ("p2r", "p2z", "ragged", "learned", "p2r_2d")
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    if "--dump" in sys.argv:
+        args.remove(sys.argv[sys.argv.index("--dump") + 1])
+    chosen = [a for a in args if a in names] or list(names)
     ctx = p2r.Context(0)
-    t = time.time()
-    d = ev.make_barrel_event(ev.P2R_THROUGHPUT)
     W = 256
-    g = _gpu_p2r(p2r, ctx, d, W)
-    r = oracle.fit_event(d, "barrel", nthreads=16)
-    report(f"p2r {ev.P2R_THROUGHPUT.name} (W={W})", g, r, "cylinder", dump=_dump("p2r"))
-    print(f"  ({time.time() - t:.0f} s)", flush=True)
-    del d, g, r
-    t = time.time()
-    d = ev.make_disk_event(ev.P2Z_THROUGHPUT)
-    g = _gpu_p2z(p2r, ctx, d)
-    r = oracle.fit_event(d, "disk", nthreads=16)
-    report(f"p2z {ev.P2Z_THROUGHPUT.name}", g, r, "plane", dump=_dump("p2z"))
-    print(f"  ({time.time() - t:.0f} s)", flush=True)
-    del d, g, r
-    t = time.time()
-    d = ev.make_ragged_event(ev.RAGGED)
-    cut = 30.0
-    g = _gpu_ragged(p2r, ctx, d, cut)
-    r = oracle.fit_ragged(d, chi2_cut=cut, nthreads=16)
-    fs = final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"])
-    report(f"ragged {ev.RAGGED.name} (chi2 cut {cut:g})", g, r, fs, dump=_dump("ragged"))
-    print(f"  ({time.time() - t:.0f} s)", flush=True)
-    del d, g, r
-    from paper_2401_14221_amd import learned
-    t = time.time()
-    mlp = p2r.Mlp(ctx)
-    mlp.load(learned.DEFAULT_CKPT)
-    d = ev.make_barrel_event(ev.LEARNED_EVAL)
-    g = _gpu_p2r(p2r, ctx, d, W, mlp=mlp)
-    r = oracle.fit_event(d, "barrel", nthreads=16)
-    report(f"p2r learned start {ev.LEARNED_EVAL.name} (W={W})", g, r, "cylinder", dump=_dump("learned"))
-    print(f"  ({time.time() - t:.0f} s)", flush=True)
+    for name in chosen:
+        t = time.time()
+        if name == "p2z":
+            d = ev.make_disk_event(ev.P2Z_THROUGHPUT)
+            g = _gpu_p2z(p2r, ctx, d)
+            r = oracle.fit_event(d, "disk", nthreads=16)
+            report(f"p2z {ev.P2Z_THROUGHPUT.name}", g, r, "plane", dump=_dump(name))
+        elif name == "ragged":
+            d = ev.make_ragged_event(ev.RAGGED)
+            cut = 30.0
+            g = _gpu_ragged(p2r, ctx, d, cut)
+            r = oracle.fit_ragged(d, chi2_cut=cut, nthreads=16)
+            fs = final_surface_of(r["par"], d["offsets"], d["surf_type"], d["surf_val"])
+            report(f"ragged {ev.RAGGED.name} (chi2 cut {cut:g})", g, r, fs, dump=_dump(name))
+        elif name == "learned":
+            mlp = p2r.Mlp(ctx)
+            mlp.load(learned.DEFAULT_CKPT)
+            d = ev.make_barrel_event(ev.LEARNED_EVAL)
+            g = _gpu_p2r(p2r, ctx, d, W, mlp=mlp)
+            r = oracle.fit_event(d, "barrel", nthreads=16)
+            report(f"p2r learned start {ev.LEARNED_EVAL.name} (W={W})", g, r, "cylinder", dump=_dump(name))
+        else:
+            u2d = name == "p2r_2d"
+            d = ev.make_barrel_event(ev.P2R_THROUGHPUT)
+            g = _gpu_p2r(p2r, ctx, d, W, update_2d=int(u2d))
+            r = oracle.fit_event(d, "barrel", nthreads=16, update_2d=u2d)
+            what = "p2r update in the hit frame" if u2d else "p2r"
+            report(f"{what} {ev.P2R_THROUGHPUT.name} (W={W})", g, r, "cylinder", dump=_dump(name))
+        print(f"  ({time.time() - t:.0f} s)", flush=True)
+        del d, g, r
     ctx.close()
-
 
 if __name__ == "__main__":
     sys.exit(main())
