@@ -1,13 +1,14 @@
 """Full-size parity report: every track of the p2r, p2z, ragged,
-learned-start and hit-frame-update benchmark workloads fitted on the GPU and
-by the FP64 oracle, compared element by element.  Prints, per workload, the
+learned-start and hit-frame-update benchmark workloads, and of p2r with the
+closed-form crossing start and with every step in FP64, fitted on the GPU
+and by the FP64 oracle, compared element by element.  Prints, per workload, the
 largest error of every output, how many covariance elements pass under each
 branch of the rule in tests/parity.py, how many tracks had a bound widened
 by the oracle's measured FP32 sensitivity, and how many end at a shallow
 incidence.
 
 Needs a GPU and the built libraries:
-  python -m tests.parity_report [p2r p2z ragged learned p2r_2d] [--dump DIR]
+  python -m tests.parity_report [p2r p2z ragged learned p2r_2d p2r_cf p2r_f64] [--dump DIR]
 (workload names select some of them, default all; --dump writes the GPU and
 oracle outputs of the tracks that fail a check to DIR/parity_fail_<name>.npz.)
 """
@@ -19,13 +20,13 @@ import time
 import numpy as np
 
 
-def _gpu_p2r(p2r, ctx, d, W, mlp=None, update_2d=0):
+def _gpu_p2r(p2r, ctx, d, W, mlp=None, update_2d=0, cyl_start=0, fp64=0):
     import torch
     n = d["par"].shape[0]
     trk = p2r.pack_tracks(d["par"], d["cov"], d["q"], W, device="cuda")
     hits = p2r.pack_hits_p2r(d["hits"], d["hitcov"], W, device="cuda")
     radii = torch.as_tensor(d["surf"], dtype=torch.float32, device="cuda")
-    opts = p2r._lib.default_opts(width=W, update_2d=update_2d)
+    opts = p2r._lib.default_opts(width=W, update_2d=update_2d, cyl_start=cyl_start, fp64=fp64)
     if mlp is not None:
         opts.mlp = mlp.handle.value
     out, chi2, st = ctx.p2r_propagate_update(n, radii, trk, hits, opts=opts)
@@ -120,13 +121,14 @@ def main():
     from synth import events as ev
     from tests.parity import final_surface_of
 
-    names = ("p2r", "p2z", "ragged", "learned", "p2r_2d")
+    names = ("p2r", "p2z", "ragged", "learned", "p2r_2d", "p2r_cf", "p2r_f64")
     args = [a for a in sys.argv[1:] if not a.startswith("--")]
     if "--dump" in sys.argv:
         args.remove(sys.argv[sys.argv.index("--dump") + 1])
     chosen = [a for a in args if a in names] or list(names)
     ctx = p2r.Context(0)
     W = 256
+    exact = {}
     for name in chosen:
         t = time.time()
         if name == "p2z":
@@ -151,13 +153,18 @@ def main():
         else:
             u2d = name == "p2r_2d"
             d = ev.make_barrel_event(ev.P2R_THROUGHPUT)
-            g = _gpu_p2r(p2r, ctx, d, W, update_2d=int(u2d))
-            r = oracle.fit_event(d, "barrel", nthreads=16, update_2d=u2d)
-            what = "p2r update in the hit frame" if u2d else "p2r"
+            g = _gpu_p2r(p2r, ctx, d, W, update_2d=int(u2d), cyl_start=int(name == "p2r_cf"),
+                         fp64=int(name == "p2r_f64"))
+            if u2d not in exact:      # the oracle has no start choice and no precision switch
+                exact[u2d] = oracle.fit_event(d, "barrel", nthreads=16, update_2d=u2d)
+            r = exact[u2d]
+            what = {"p2r_2d": "p2r update in the hit frame", "p2r_cf": "p2r closed-form crossing start",
+                    "p2r_f64": "p2r every step in FP64"}.get(name, "p2r")
             report(f"{what} {ev.P2R_THROUGHPUT.name} (W={W})", g, r, "cylinder", dump=_dump(name))
         print(f"  ({time.time() - t:.0f} s)", flush=True)
         del d, g, r
     ctx.close()
+
 
 if __name__ == "__main__":
     sys.exit(main())
