@@ -55,7 +55,12 @@ hipError_t launch_fit(const Variant& v, const FitLaunch& a, const Params& P, hip
 constexpr int RAG_W = 64;
 constexpr int RAG_ETA_BINS = 8;
 constexpr int RAG_FIELDS = 11;      // surface type, surface value, hit (3), hit covariance (6)
-constexpr int RAG_TPB = 1024;       // tracks per workgroup in the sort kernels
+// Tracks per workgroup in the sort kernels.  Each workgroup ends with one
+// global atomic per key it holds, and the atomics on one key serialise, so
+// fewer, larger workgroups sort faster: at 10^6 tracks the histogram and
+// scatter take 25 + 33 us with 1024 tracks per workgroup, 19 + 20 us with
+// 4096 (245 workgroups, 16 tracks per thread).
+constexpr int RAG_TPB = 4096;
 constexpr int RAG_LSTRIDE = RAG_W + 1;  // floats per staged LDS row (one pad float)
 
 struct RaggedLaunch {
