@@ -3,9 +3,11 @@
 Default workload: p2r, 100 events x 9,600 tracks x 20 barrel layers at
 r = 2.5..110 cm (19.2 M track-layers per step), FP32 on the GPU, inputs
 resident in HBM.  A step is one launch of the fused fit over the whole
-workload.  Protocol (paper, Section 4): W untimed warm-up steps, then K
-timed steps bracketed by device synchronisation; the kernel's own time is
-taken with HIP events on the stream it is launched on.
+workload.  Protocol (paper, Section 4): untimed warm-up steps (back to back
+for --settle-ms, so that the GPU's clock has settled after the idle time of
+input generation, then W more), then K timed steps bracketed by device
+synchronisation; the kernel's own time is taken with HIP events on the
+stream it is launched on.
 
 Prints ONE JSON line.  Besides the headline p2r figure it carries the
 roofline of the fit kernel, the FP64 CPU oracle timed on a bounded sample
@@ -25,7 +27,9 @@ import numpy as np
 METRIC = "track-layer updates/sec at 1 GPU and % HBM roofline; learned vs plain at 1e-4 rel"
 UNIT = "track-layers/s"
 HBM_PEAK_GBPS = 8000.0
-# FP32 vector peak of MI355X (published; counts an FMA as 2 flops)
+# FP32 vector peak of MI355X (published; counts an FMA as 2 flops): one wave64
+# FP32 instruction per 2 cycles per SIMD at 2.4 GHz, which plain (non-packed)
+# FP32 instructions reach when a SIMD holds enough waves
 FP32_PEAK_TFLOPS = 157.3
 # dense BF16 matrix-core peak of MI355X, and the path-length network's work per
 # evaluation (7 -> 64 -> 64 -> 1: 4,608 multiply-adds, 2 flops each)
@@ -45,8 +49,11 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=20,
-                    help="untimed steps first: the GPU clocks take some tens of launches to settle")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed steps before the timed ones")
+    ap.add_argument("--settle-ms", type=float, default=200.0,
+                    help="before the warm-up steps, run the step back to back for this long, untimed: after an "
+                         "idle period the GPU's clock needs some tens of milliseconds of sustained work to "
+                         "settle, and a p2r step is 0.3 ms")
     ap.add_argument("--no-extra", action="store_true", help="headline p2r figure only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
@@ -100,12 +107,33 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+SETTLE_S = 0.2          # set from --settle-ms
+LAST_SETTLE_STEPS = 0   # untimed settle steps of the last timed() call (profiles locate the timed launches)
+
+
+def settle(fn):
+    """Run `fn` back to back, untimed, for SETTLE_S seconds of wall time (in
+    rounds of 8 steps, each waited for, so that the host does not queue far
+    ahead of the GPU).  Returns the number of steps run."""
+    import torch
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < SETTLE_S:
+        for _ in range(8):
+            fn()
+        n += 8
+        torch.cuda.synchronize()
+    return n
+
+
 def timed(fn, steps, warmup, stream):
     """Mean device time of one step over `steps` steps (HIP events on `stream`
-    around them, after `warmup` untimed steps and a synchronisation), the
-    host wall time per step, and the standard deviation of the per-step
-    times (events recorded between the steps)."""
+    around them, after SETTLE_S seconds of untimed steps, `warmup` more and a
+    synchronisation), the host wall time per step, and the standard deviation
+    of the per-step times (events recorded between the steps)."""
     import torch
+    global LAST_SETTLE_STEPS
+    LAST_SETTLE_STEPS = settle(fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -143,6 +171,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the fit needs no "
                                    "cross-GPU exchange: shard tracks by event, one process per GPU)"}))
         sys.exit(2)
+    global SETTLE_S
+    SETTLE_S = max(0.0, args.settle_ms) * 1e-3
     import torch
     import paper_2401_14221_amd as p2r
     from synth import events as ev
@@ -217,6 +247,7 @@ def main():
     log(f"p2r: {ms:.3f} ms/step, {value:.3e} track-layers/s, {gbps:.0f} GB/s algorithmic, {tflops:.1f} TFLOP/s")
     res = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "settle_ms": args.settle_ms, "settle_steps": LAST_SETTLE_STEPS,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded RK4 truth simulation, smeared hits)",
         "config": {"workload": cfg.name, "events": cfg.n_events, "tracks_per_event": cfg.n_tracks,
@@ -304,6 +335,7 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
         ctx.p2z_propagate_update(n, zs, trk, hits, out=o, opts=opts, stream=stream)
 
     ms, _, _ = timed(step, args.steps, args.warmup, stream)
+    settle_steps = LAST_SETTLE_STEPS
     opts_64 = p2r._lib.default_opts(fp64=1)
 
     def step_64():
@@ -333,7 +365,7 @@ def p2z_leg(ctx, args, stream, ev, p2r, dev):
     tl = n * L
     alg = n * TRACK_BYTES + tl * HIT_BYTES
     out = {"workload": cfg.name, "variant": ctx.variant_name(1),
-           "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT,
+           "ms_per_step": ms, "value": tl / (ms * 1e-3), "unit": UNIT, "settle_steps": settle_steps,
            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
            "tflops": tl * P2Z_FLOP_PER_TL / (ms * 1e-3) / 1e12,
            "with_transfers": {"ms_per_step": ms_x, "value": tl / (ms_x * 1e-3),
@@ -381,7 +413,7 @@ def ragged_leg(ctx, args, stream, ev, p2r, dev):
     ms_r, _, _ = timed(rstep, args.steps, args.warmup, stream)
     alg_r = n * (TRACK_BYTES + 8) + H * (HIT_BYTES + 5)
     out = {"workload": cfg.name, "ms_per_step": ms_r, "value": H / (ms_r * 1e-3), "unit": UNIT,
-           "track_layers": H, "hbm_frac": alg_r / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+           "settle_steps": LAST_SETTLE_STEPS, "track_layers": H, "hbm_frac": alg_r / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBPS,
            "variant": ctx.variant_name(2),
            "note": "one HIP graph per step: counting sort of the tracks, then the fit with the hits staged "
                    "through LDS"}
