@@ -1,0 +1,41 @@
+"""The VALU issue rate that the fit kernels' roofline is quoted against.
+
+MI355X's published FP32 vector peak, 157.3 TFLOP/s, is one wave64 FP32
+instruction per 2 cycles per SIMD at 2.4 GHz.  The probe (tests/probes)
+measures that plain (non-packed) FP32 instructions reach about that rate
+when a SIMD interleaves 8 waves, that one wave alone issues far slower, and
+that FP64 FMA takes twice as long as FP32 (the 78.6 TFLOP/s FP64 peak)."""
+import os
+import subprocess
+
+import pytest
+
+from tests.probes import build as probe
+
+pytestmark = pytest.mark.gpu
+
+
+def _rates():
+    if not os.path.exists(probe.EXE):
+        pytest.fail("the probe is not built: run __graft_entry__.build()")
+    r = subprocess.run([probe.EXE], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    print(r.stdout, flush=True)
+    rates = {}
+    for line in r.stdout.splitlines():
+        f = line.split()
+        if f and f[0].startswith("v_") and len(f) == 5:
+            rates[f[0]] = [float(x) for x in f[1:]]      # 1, 2, 4, 8 waves per SIMD
+    assert set(rates) == {"v_fmac_f32", "v_add_f32", "v_xor_b32", "v_fma_f64"}
+    return rates
+
+
+def test_fp32_issues_near_two_cycles_with_enough_waves():
+    rates = _rates()
+    for kind in ("v_fmac_f32", "v_add_f32", "v_xor_b32"):
+        one, two, four, eight = rates[kind]
+        assert 1.9 <= eight <= 3.0, (kind, rates[kind])      # measured 2.4-2.5; 4 would be a 16-lane SIMD
+        assert one > 2 * eight, (kind, rates[kind])          # one wave cannot issue every 2 cycles
+        assert one > two > four > eight, (kind, rates[kind])
+    f64 = rates["v_fma_f64"][3]
+    assert f64 > 1.6 * rates["v_fmac_f32"][3], rates
