@@ -34,7 +34,9 @@ def test_fp32_issues_near_two_cycles_with_enough_waves():
     rates = _rates()
     for kind in ("v_fmac_f32", "v_add_f32", "v_xor_b32"):
         one, two, four, eight = rates[kind]
-        assert 1.9 <= eight <= 3.0, (kind, rates[kind])      # measured 2.4-2.5; 4 would be a 16-lane SIMD
+        # measured 2.4-2.5 (2 at the peak); a 16-lane SIMD would need at least 4,
+        # and the bound leaves room for a box whose clock runs below 2.4 GHz
+        assert 1.9 <= eight <= 3.4, (kind, rates[kind])
         assert one > 2 * eight, (kind, rates[kind])          # one wave cannot issue every 2 cycles
         assert one > two > four > eight, (kind, rates[kind])
     f64 = rates["v_fma_f64"][3]
